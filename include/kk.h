@@ -1,0 +1,250 @@
+/*
+ * kk.h - C ABI of the KK (far-field compressive) plane-wave beamforming library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Khetan & Mertz, "Far-field compressive ultrasound beamforming".  Multi-angle
+ * linear-array channel data RF_u(u_l, t) (one record per transmit plane wave theta_i) are
+ * decomposed into virtual receive plane waves RF_theta(theta_o, t) (Eq. 3), and images are
+ * formed pixel by pixel by summing each selected (theta_i, theta_o) pair at its far-field
+ * delay (Eq. 5).  Receive angles follow Eq. 6 (shifted vernier) or Eq. 7 (confocal); sets
+ * of Eq. 6 are compounded by Eq. 8 / Eq. 9.  Conventional CPWC delay-and-sum (Eq. 4) is
+ * provided on the same data as the comparator.
+ *
+ * Conventions (all entry points)
+ *   - Sizes are int32, angles are radians (FP64), lengths metres, times seconds (SI).
+ *   - Arrays are row-major, last index fastest.  Complex samples are interleaved float pairs
+ *     (re, im), i.e. "float2".
+ *   - Element l sits at u_l = ((2l - (L-1)) pitch) / 2 on z = 0 (origin at the array centre).
+ *     Pixel (k, m) sits at x_k = x0 + k dx, z_m = z0 + m dz.  Sample n of a record is time
+ *     t0 + n / fs; t = 0 is when the transmitted wavefront crosses the origin.
+ *   - All buffers are owned by the caller.  "dev" pointers are device memory on the current
+ *     HIP device, "host" pointers are host memory.  The library allocates no device memory,
+ *     keeps no global state and is re-entrant.
+ *   - Host entry points are synchronous.  Device entry points validate their arguments on
+ *     the host, enqueue work on `stream` (a hipStream_t; NULL = the default stream) and
+ *     return without synchronising; faults surface at the caller's next synchronisation.
+ *   - Every entry point returns a kk_status; on error nothing is written to outputs unless
+ *     stated (capacity errors write the required size).
+ */
+#ifndef KK_H
+#define KK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Acquisition geometry: L elements of pitch pitch_m, T samples per record at fs_hz, sound
+ * speed c_mps, time of sample 0 t0_s. */
+typedef struct kk_geom {
+    int32_t L;
+    int32_t T;
+    double pitch_m;
+    double c_mps;
+    double fs_hz;
+    double t0_s;
+} kk_geom;
+
+/* Image grid: X lateral by Z axial pixels, x_k = x0_m + k dx_m, z_m = z0_m + m dz_m. */
+typedef struct kk_grid {
+    int32_t X;
+    int32_t Z;
+    double x0_m;
+    double dx_m;
+    double z0_m;
+    double dz_m;
+} kk_grid;
+
+typedef enum kk_status {
+    KK_OK = 0,
+    KK_E_NULL = -1,        /* a required pointer is NULL                                  */
+    KK_E_ARG = -2,         /* an argument is out of its documented range                  */
+    KK_E_CAPACITY = -3,    /* an output array is too small; required size written back    */
+    KK_E_WORKSPACE = -4,   /* workspace or plan buffer too small or not a valid plan      */
+    KK_E_RANGE = -5,       /* a delay does not fit the int32 fixed-point tables           */
+    KK_E_HIP = -6,         /* a HIP runtime call or kernel launch failed                  */
+    KK_E_UNSUPPORTED = -7  /* valid request this build does not implement                 */
+} kk_status;
+
+/* Receive-angle selection schemes (Sec. II-C, II-D). */
+typedef enum kk_scheme {
+    KK_SCHEME_SHIFTED = 0,      /* Eq. 6: one set per j in j_list, j in [0, floor(N/2)]      */
+    KK_SCHEME_CONFOCAL = 1,     /* Eq. 7: one set                                            */
+    KK_SCHEME_SAME = 2,         /* receive angles = transmit angles (redundant control)      */
+    KK_SCHEME_FULL_UNIFORM = 3  /* M angles uniform over +-(theta_max + dth_i): dense bank   */
+} kk_scheme;
+
+typedef enum kk_precision {
+    KK_PREC_FP32 = 0            /* FP32 transforms and contraction (the parity path)         */
+} kk_precision;
+
+typedef enum kk_compound_mode {
+    KK_COMPOUND_COHERENT = 0,   /* Eq. 8: I = |sum_s B_s|^2                                   */
+    KK_COMPOUND_INCOHERENT = 1  /* Eq. 9: I = sum_s |B_s|^2                                   */
+} kk_compound_mode;
+
+/* ---------------------------------------------------------------------------------------
+ * kk_select_pairs (host) - transmit angles, distinct receive angles and the pair list.
+ *
+ * Sec. II-B: theta_i = ((2i - (N-1)) theta_max) / (N-1), dth_i = 2 theta_max / (N-1).
+ * Eq. 6: theta_o = sgn(o) dth_i (2|o|/M + j), o = -floor(M/2)..floor(M/2), one set per j.
+ * Eq. 7: theta_o = sgn(o) dth_i (2|o|/M + mod(|o|, floor(N/2))), one set.
+ * Angles are exact rationals theta_o / dth_i = rx_num / rx_den (lowest terms, den > 0);
+ * FP64 values are (n dth_i) / M with n = sgn(o)(2|o| + j M) (Eq. 7 analogue).  Distinct
+ * receive angles are de-duplicated on the rationals and sorted ascending.  Pairs are
+ * (i, o, s) triples, ordered by set s, then receive index o, then transmit index i; an
+ * angle shared by several sets gets one slot per set.  compression = L / (J * M_set)
+ * (Sec. II-C), M_set = receive angles per set (2 floor(M/2) + 1 for Eq. 6/7).
+ *
+ *   scheme      kk_scheme
+ *   L, N        elements (>= 1), transmit angles (>= 2)
+ *   theta_max   half range of the transmit fan, (0, pi/2)
+ *   M           Eq. 6/7: per-set parameter (>= 1); SAME: ignored; FULL_UNIFORM: bank size (>= 2)
+ *   j_list, J   Eq. 6 shifts (J >= 1 entries); ignored otherwise (may be NULL)
+ *   tx_theta    host out [N]
+ *   rx_theta, rx_num, rx_den   host out [cap_rx]; *M_out = number of distinct angles
+ *   pairs       host out [cap_p][3] = {i, o, s}; *P_out = number of pair slots
+ *   S_out       number of sets;  compression  as above
+ * Errors: KK_E_NULL, KK_E_ARG (bad scheme/N/M/j/theta_max, any angle reaching 90 deg),
+ * KK_E_CAPACITY (cap_rx or cap_p too small; *M_out and *P_out hold the required sizes).
+ * ------------------------------------------------------------------------------------- */
+int32_t kk_select_pairs(int32_t scheme, int32_t L, int32_t N, double theta_max, int32_t M,
+                        const int32_t* j_list, int32_t J,
+                        double* tx_theta,
+                        double* rx_theta, int32_t* rx_num, int32_t* rx_den, int32_t cap_rx,
+                        int32_t* M_out,
+                        int32_t* pairs, int32_t cap_p, int32_t* P_out,
+                        int32_t* S_out, double* compression);
+
+/* ---------------------------------------------------------------------------------------
+ * kk_build_luts (host) - separable Q16.16 delay tables (Sec. II-F) and the Q.22 shear
+ * table of Eq. 3.  Values in samples; FP64, no contraction; rint = round half to even:
+ *   lut1[i][k] = rint(((x_k sin th_i) / c) fs 65536)            [N][X]
+ *   lut2[i][m] = rint(((z_m cos th_i) / c) fs 65536)            [N][Z]
+ *   lut3[o][k] = rint(((-(x_k - x_ref) sin th_o) / c) fs 65536) [M][X]
+ *   lut4[o][m] = rint(((z_m cos th_o) / c) fs 65536)            [M][Z]
+ *   t0_q      = rint((-t0) fs 65536)
+ *   shift_q[o][l] = rint(((d_l sin th_o) / c) fs 2^22)         [M][L]
+ * x_ref = u_0 for th_o >= 0, u_{L-1} for th_o < 0; d_l = u_l - u_0 (th_o > 0),
+ * u_l - u_{L-1} (th_o < 0), 0 (th_o = 0).  Eq. 3 advances element l by d_l sin(th_o)/c;
+ * by stationary phase a scatterer at (x, z) then appears at
+ * tau_in + [z cos th_o - (x - x_ref) sin th_o] / c, which lut3 + lut4 encode (Eq. 5's
+ * s_o.r/c with th_o mirrored and the origin at the reference edge).
+ * *tpad = smallest power of two >= T + ceil(max shift_q / 2^22): the FFT length of Eq. 3's
+ * Fourier-shift evaluation (all advanced reads past the record then see zero padding).
+ * Any output pointer may be NULL to skip it.  Errors: KK_E_NULL (g, grid, angles),
+ * KK_E_ARG (non-positive sizes, c, fs, pitch, dx, dz), KK_E_RANGE (an entry or a composite
+ * delay lut1+lut2+lut3+lut4+t0_q outside int32).
+ * ------------------------------------------------------------------------------------- */
+int32_t kk_build_luts(const kk_geom* g, const kk_grid* grid,
+                      const double* tx_theta, int32_t N, const double* rx_theta, int32_t M,
+                      int32_t* lut1, int32_t* lut2, int32_t* lut3, int32_t* lut4,
+                      int32_t* t0_q, int32_t* shift_q, int32_t* tpad);
+
+/* kk_build_das_rx (host) - DAS receive delays of Eq. 4 (Sec. II-F's third table):
+ *   das_rx[k][l][m] = rint((sqrt(dx dx + z_m z_m) / c) fs 65536),  dx = x_k - u_l   [X][L][Z]
+ * Errors: KK_E_NULL, KK_E_ARG, KK_E_RANGE. */
+int32_t kk_build_das_rx(const kk_geom* g, const kk_grid* grid, int32_t* das_rx);
+
+/* ---------------------------------------------------------------------------------------
+ * kk_beamform_plan (host) - per-geometry beamforming plan for kk_beamform.
+ *
+ * Folds the four tables per pair, A[p][x] = lut1[i][x] + lut3[o][x] + t0_q and
+ * B[p][z] = lut2[i][z] + lut4[o][z] (exact integer adds: the composite Q16.16 delay of
+ * Eq. 5 is A[p][x] + B[p][z]), groups the pairs by set and records, for every pair and
+ * pixel tile, the exact span of record samples the tile reads.  The plan is an opaque
+ * byte buffer; copy it to device memory unchanged and pass it to kk_beamform.
+ *   pairs [P][3] = {i, o, s} host, 0 <= i < N, 0 <= o < M, 0 <= s < S, every set non-empty
+ *   lut1..lut4, t0_q  host tables from kk_build_luts
+ *   T           samples per RF_theta record
+ *   plan        host out, plan_bytes long; *plan_bytes_out = required size (always written)
+ * Errors: KK_E_NULL, KK_E_ARG (sizes, pair entries), KK_E_RANGE (composite delay outside
+ * int32), KK_E_CAPACITY (plan_bytes too small, required size in *plan_bytes_out),
+ * KK_E_UNSUPPORTED (a tile would need more record samples than fit the on-chip window).
+ * Passing plan = NULL with plan_bytes = 0 queries the size (returns KK_E_CAPACITY).
+ * ------------------------------------------------------------------------------------- */
+int32_t kk_beamform_plan(const int32_t* pairs, int32_t P, int32_t S, int32_t N, int32_t M,
+                         int32_t T,
+                         const int32_t* lut1, const int32_t* lut2, const int32_t* lut3,
+                         const int32_t* lut4, int32_t t0_q, const kk_grid* grid,
+                         void* plan, size_t plan_bytes, size_t* plan_bytes_out);
+
+/* ---------------------------------------------------------------------------------------
+ * kk_decompose (device) - Eq. 3 receive plane-wave decomposition, evaluated as Sec. II-F
+ * describes: analytic (Hilbert) spectrum of each zero-padded record (mask: DC x1,
+ * bins 1..tpad/2-1 x2, Nyquist x1, negative bins 0), per temporal-frequency bin k the
+ * complex contraction
+ *   Y[i][o][k] = sum_l A[i][l][k] exp(2 pi i ((k shift_q[o][l]) mod (tpad 2^22)) / (tpad 2^22))
+ * (Fourier shift theorem), and the inverse transform
+ *   rf_theta[i][o][n] = (1/tpad) sum_{k <= tpad/2} Y[i][o][k] exp(+2 pi i k n / tpad), n < T.
+ *   rf        dev in  int16 [N][L][T]
+ *   shift_q   dev in  int32 [M][L] (kk_build_luts)
+ *   tpad      FFT length from kk_build_luts: power of two, T < tpad <= 8192... see limits
+ *   precision KK_PREC_FP32
+ *   rf_theta  dev out complex float [N][M][T]
+ *   ws        dev workspace of at least kk_decompose_workspace_bytes() bytes
+ * Limits: 1 <= N, 1 <= M, 1 <= L <= 1024, 1 <= T < tpad, tpad in {256, ..., 8192}.
+ * Errors: KK_E_NULL, KK_E_ARG, KK_E_WORKSPACE, KK_E_UNSUPPORTED (precision), KK_E_HIP.
+ * ------------------------------------------------------------------------------------- */
+size_t kk_decompose_workspace_bytes(const kk_geom* g, int32_t N, int32_t M, int32_t tpad,
+                                    int32_t precision);
+int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q,
+                     int32_t M, int32_t tpad, int32_t precision, float* rf_theta,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * kk_beamform (device) - Eq. 5 per set:
+ *   image[s][k][m] = sum_{p in set s} v_p,  q = A[p][k] + B[p][m] (Q16.16 samples),
+ *   idx = floor(q / 65536), w = (q mod 65536) / 65536,
+ *   v_p = (1 - w) R_p[idx] + w R_p[idx + 1],  R_p = rf_theta[i_p][o_p], zero outside [0, T).
+ *   rf_theta  dev in complex float [N][M][T]
+ *   plan      dev copy of a kk_beamform_plan buffer for the same N, M, T
+ *   image     dev out complex float [S][X][Z]
+ *   intensity dev out float [X][Z] or NULL: Eq. 8 (mode COHERENT) or Eq. 9 (INCOHERENT)
+ *             of the S images, written in the same pass
+ * Errors: KK_E_NULL, KK_E_ARG (N, M, T differ from the plan's), KK_E_WORKSPACE (plan header
+ * invalid), KK_E_HIP.  The plan header is read from host memory: pass its host copy too.
+ * ------------------------------------------------------------------------------------- */
+int32_t kk_beamform(const float* rf_theta, int32_t N, int32_t M, int32_t T,
+                    const void* plan_host, const void* plan_dev, size_t plan_bytes,
+                    float* image, float* intensity, int32_t mode, void* stream);
+
+/* kk_compound (device) - Eq. 8 / Eq. 9 of S per-set images image [S][X][Z] (complex)
+ * into intensity [X][Z] (float).  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
+int32_t kk_compound(const float* image, int32_t S, int32_t X, int32_t Z, int32_t mode,
+                    float* intensity, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * das_plan (host) - per-geometry plan for das_beamform (Eq. 4): folded transmit delays
+ * A[i][x] = lut1[i][x] + t0_q, B[i][z] = lut2[i][z], the receive table das_rx re-laid out
+ * for coalesced reads, and per (transmit, element, tile) the exact record span.
+ *   lut1 [N][X], lut2 [N][Z], das_rx [X][L][Z] host (kk_build_luts / kk_build_das_rx)
+ * Same buffer protocol and errors as kk_beamform_plan.
+ * ------------------------------------------------------------------------------------- */
+int32_t das_plan(int32_t N, const kk_geom* g, const int32_t* lut1, const int32_t* lut2,
+                 const int32_t* das_rx, int32_t t0_q, const kk_grid* grid,
+                 void* plan, size_t plan_bytes, size_t* plan_bytes_out);
+
+/* das_beamform (device) - conventional CPWC delay-and-sum, Eq. 4, on the analytic channel
+ * data (FFT length tpad_das = smallest power of two >= T, same mask as kk_decompose):
+ *   image[k][m] = sum_{i, l} lerp(RFa[i][l], A[i][k] + B[i][m] + das_rx[k][l][m])
+ *   rf        dev in int16 [N][L][T]
+ *   plan      host and dev copies of a das_plan buffer
+ *   image     dev out complex float [X][Z]
+ *   ws        dev workspace of at least das_workspace_bytes() bytes
+ * Errors: KK_E_NULL, KK_E_ARG, KK_E_WORKSPACE, KK_E_HIP. */
+size_t das_workspace_bytes(const kk_geom* g, int32_t N);
+int32_t das_beamform(const int16_t* rf, int32_t N, const kk_geom* g,
+                     const void* plan_host, const void* plan_dev, size_t plan_bytes,
+                     float* image, void* ws, size_t ws_bytes, void* stream);
+
+/* Human-readable name of a kk_status value (static string, never NULL). */
+const char* kk_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KK_H */

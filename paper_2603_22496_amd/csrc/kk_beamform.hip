@@ -1,0 +1,323 @@
+// Delay-gather beamforming kernels for gfx950: KK (Eq. 5) per set, and the Eq. 8 / Eq. 9
+// compounding epilogue.
+//
+// One workgroup = one 64 (lateral) x 16 (axial) pixel tile of one set, 16 wave64s:
+// 4 pair groups x 4 axial quarters.  Lane k of a wave owns lateral pixel k of the tile and
+// four consecutive axial pixels, so neighbouring lanes read neighbouring record samples
+// (adjacent lateral pixels differ by at most ~1 sample of delay at lambda/2 pitch) and the
+// LDS gather is broadcast- or stride-1.  Pairs are processed in batches: for every pair of a
+// batch the workgroup stages into LDS
+//   - the record window the tile touches, as 16-byte entries (R[n], (R[n+1]-R[n]) 2^-16),
+//     n = lo .. lo+cap-1, zero outside [0, T) (plan: lo is exact per pair and tile),
+//   - the lateral delays A[p][x] with the window start and the slot's LDS position folded in,
+//   - the 16 axial delays B[p][z].
+// Then each pixel-pair costs one integer add (q = A + B), one SDWA shift that turns the
+// integer part of q into the LDS byte address, one SDWA convert of the 16-bit fraction,
+// one ds_read_b128, and two adds plus two FMAs:  acc += R[idx] + frac * (R[idx+1]-R[idx]) 2^-16,
+// which is (1 - w) R[idx] + w R[idx+1] with w = frac / 65536.
+// The four pair groups are reduced through LDS at the end.  Batches are double-buffered:
+// the global loads of batch b+1 are issued before batch b is gathered.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kk.h"
+#include "kk_plan.h"
+
+namespace kk {
+namespace {
+
+constexpr int kWaves = 16;
+constexpr int kThreads = kWaves * 64;
+constexpr int kGroups = 4;       // pair groups per workgroup
+constexpr int kRows = 4;         // axial pixels per lane
+
+struct __attribute__((aligned(8))) F4a8 {
+    float x, y, z, w;
+};
+
+// (q >> 16) << 4 in one VALU op: SDWA selects the upper 16 bits of q as the shift source.
+__device__ __forceinline__ uint32_t entry_byte_offset(uint32_t q) {
+    uint32_t a;
+    asm("v_lshlrev_b32_sdwa %0, 4, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+        : "=v"(a)
+        : "v"(q));
+    return a;
+}
+
+// Maps the launch index onto (set, tile) so that each of the 8 XCDs (workgroups are dealt to
+// XCDs round-robin) receives a contiguous run of tiles: tiles are numbered depth-major, so an
+// XCD's L2 holds only its depth band of every record.
+__device__ __forceinline__ int xcd_remap(int id, int total) {
+    const int xcd = id & 7, k = id >> 3;
+    const int base = total >> 3, rem = total & 7;
+    return xcd * base + (xcd < rem ? xcd : rem) + k;
+}
+
+template <int CAP, int PB>
+struct Lds {
+    static constexpr int kWinBytes = 2 * PB * CAP * 16;
+    static constexpr int kABytes = 2 * PB * 64 * 4;
+    static constexpr int kBBytes = 2 * PB * 16 * 4;
+    static constexpr int kBytes = kWinBytes + kABytes + kBBytes;
+    static_assert(kBytes <= 160 * 1024, "LDS budget");
+    static_assert(kWinBytes / 16 < 65536, "entry index must fit 16 bits");
+    static_assert(3 * 256 * kRows * 8 <= kBytes, "reduction scratch fits the buffers");
+};
+
+// Window rows staged by one wave: lanes cover 64 consecutive entries per row.
+template <int CAP>
+struct Prefetch {
+    F4a8 v[2][CAP / 64];  // (R[n], R[n+1]) per row, up to two slots per wave
+    int32_t a[2];
+    int32_t b[2];
+};
+
+template <int CAP, int PB>
+__device__ __forceinline__ void load_batch(Prefetch<CAP>& pf, const float2* __restrict__ rec,
+                                           const int32_t* __restrict__ plan, int tile, int q0, int nb,
+                                           int wave, int lane, int T, int P, int xpad, int zpad, int xt,
+                                           int zt, int off_rec, int off_a, int off_b, int off_lo) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int j = wave + u * kWaves;
+        if (j < nb) {
+            const int q = q0 + j;
+            const int lo = plan[off_lo + tile * P + q];
+            const float2* rp = rec + (size_t)plan[off_rec + q] * T;
+#pragma unroll
+            for (int r = 0; r < CAP / 64; ++r) {
+                const int n = lo + r * 64 + lane;
+                F4a8 v;
+                if ((unsigned)n < (unsigned)(T - 1)) {
+                    v = *reinterpret_cast<const F4a8*>(rp + n);
+                } else {
+                    float2 a = ((unsigned)n < (unsigned)T) ? rp[n] : make_float2(0.f, 0.f);
+                    float2 b = ((unsigned)(n + 1) < (unsigned)T) ? rp[n + 1] : make_float2(0.f, 0.f);
+                    v.x = a.x;
+                    v.y = a.y;
+                    v.z = b.x;
+                    v.w = b.y;
+                }
+                pf.v[u][r] = v;
+            }
+            pf.a[u] = plan[off_a + q * xpad + xt * 64 + lane];
+            pf.b[u] = lane < 16 ? plan[off_b + q * zpad + zt * 16 + lane] : 0;
+        }
+    }
+}
+
+template <int CAP, int PB>
+__device__ __forceinline__ void store_batch(const Prefetch<CAP>& pf, unsigned char* lds, int buf, int nb,
+                                            const int32_t* __restrict__ plan, int tile, int q0, int wave,
+                                            int lane, int P, int off_lo) {
+    using L = Lds<CAP, PB>;
+    float4* win = reinterpret_cast<float4*>(lds);
+    int32_t* aslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes);
+    int32_t* bslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes + L::kABytes);
+    const float scale = 1.0f / 65536.0f;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int j = wave + u * kWaves;
+        if (j < nb) {
+            const int slot = buf * PB + j;
+            const int lo = plan[off_lo + tile * P + q0 + j];
+#pragma unroll
+            for (int r = 0; r < CAP / 64; ++r) {
+                const F4a8 v = pf.v[u][r];
+                win[slot * CAP + r * 64 + lane] =
+                    make_float4(v.x, v.y, (v.z - v.x) * scale, (v.w - v.y) * scale);
+            }
+            // integer part of (A + B) becomes the entry index of the sample inside LDS
+            aslot[slot * 64 + lane] = (int32_t)((uint32_t)pf.a[u] + ((uint32_t)(slot * CAP - lo) << 16));
+            if (lane < 16) bslot[slot * 16 + lane] = pf.b[u];
+        }
+    }
+}
+
+template <int CAP, int PB>
+__global__ __launch_bounds__(kThreads) void kk_gather_kernel(const float2* __restrict__ rec,
+                                                             const int32_t* __restrict__ plan,
+                                                             float2* __restrict__ image, int n_arg,
+                                                             int m_arg, int t_arg) {
+    using L = Lds<CAP, PB>;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
+    // a device plan that does not describe this call is ignored (uniform early exit)
+    if (plan[PW_MAGIC] != kPlanMagic || plan[PW_KIND] != kPlanKindKK || plan[PW_N] != n_arg ||
+        plan[PW_M] != m_arg || plan[PW_T] != t_arg || plan[PW_CAP] != CAP || plan[PW_PB] != PB)
+        return;
+    const int T = plan[PW_T], P = plan[PW_P], S = plan[PW_S], X = plan[PW_X], Z = plan[PW_Z];
+    const int nxt = plan[PW_NXT], nzt = plan[PW_NZT], xpad = plan[PW_XPAD], zpad = plan[PW_ZPAD];
+    const int off_set = plan[PW_OFF_SET], off_rec = plan[PW_OFF_REC], off_a = plan[PW_OFF_A],
+              off_b = plan[PW_OFF_B], off_lo = plan[PW_OFF_LO];
+    const int ntiles = nxt * nzt;
+    const int r = xcd_remap(blockIdx.x, ntiles * S);
+    const int s = r / ntiles, tile = r - s * ntiles;
+    const int zt = tile / nxt, xt = tile - zt * nxt;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int group = wave >> 2, quarter = wave & 3;
+    const int p_begin = plan[off_set + s], p_end = plan[off_set + s + 1];
+
+    float2 acc[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) acc[k] = make_float2(0.f, 0.f);
+
+    const float4* win = reinterpret_cast<const float4*>(lds);
+    const int32_t* aslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes);
+    const int32_t* bslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes + L::kABytes);
+
+    Prefetch<CAP> pf;
+    int q0 = p_begin;
+    int nb = min(PB, p_end - q0);
+    load_batch<CAP, PB>(pf, rec, plan, tile, q0, nb, wave, lane, T, P, xpad, zpad, xt, zt, off_rec, off_a, off_b,
+                        off_lo);
+    store_batch<CAP, PB>(pf, lds, 0, nb, plan, tile, q0, wave, lane, P, off_lo);
+    __syncthreads();
+    int buf = 0;
+    constexpr int kPerGroup = PB / kGroups;
+    while (true) {
+        const int q1 = q0 + nb;
+        const int nb1 = min(PB, p_end - q1);
+        if (nb1 > 0)
+            load_batch<CAP, PB>(pf, rec, plan, tile, q1, nb1, wave, lane, T, P, xpad, zpad, xt, zt, off_rec, off_a,
+                                off_b, off_lo);
+        // gather: this group's contiguous share of the batch
+        const int j0 = group * kPerGroup;
+        const int j1 = min(j0 + kPerGroup, nb);
+        for (int j = j0; j < j1; ++j) {
+            const int slot = buf * PB + j;
+            const uint32_t a = (uint32_t)aslot[slot * 64 + lane];
+            const int4 b = *reinterpret_cast<const int4*>(&bslot[slot * 16 + quarter * 4]);
+            const uint32_t bq[4] = {(uint32_t)b.x, (uint32_t)b.y, (uint32_t)b.z, (uint32_t)b.w};
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                const uint32_t q = a + bq[k];
+                const float w = (float)(q & 0xFFFFu);
+                const float4 e = *reinterpret_cast<const float4*>(reinterpret_cast<const unsigned char*>(win) +
+                                                                  entry_byte_offset(q));
+                acc[k].x += e.x;
+                acc[k].y += e.y;
+                acc[k].x = __builtin_fmaf(w, e.z, acc[k].x);
+                acc[k].y = __builtin_fmaf(w, e.w, acc[k].y);
+            }
+        }
+        if (nb1 <= 0) break;
+        store_batch<CAP, PB>(pf, lds, buf ^ 1, nb1, plan, tile, q1, wave, lane, P, off_lo);
+        __syncthreads();
+        buf ^= 1;
+        q0 = q1;
+        nb = nb1;
+    }
+    // reduce the four pair groups
+    __syncthreads();
+    float2* red = reinterpret_cast<float2*>(lds);
+    const int slotpix = (quarter * kRows) * 64 + lane;  // + k * 64
+    if (group > 0) {
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) red[(group - 1) * 1024 + slotpix + k * 64] = acc[k];
+    }
+    __syncthreads();
+    if (group == 0) {
+        const int x = xt * 64 + lane;
+        const int z0 = zt * 16 + quarter * kRows;
+        if (x < X) {
+            float2* out = image + ((size_t)s * X + x) * Z;
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) {
+                float2 v = acc[k];
+#pragma unroll
+                for (int g = 0; g < kGroups - 1; ++g) {
+                    const float2 t = red[g * 1024 + slotpix + k * 64];
+                    v.x += t.x;
+                    v.y += t.y;
+                }
+                if (z0 + k < Z) out[z0 + k] = v;
+            }
+        }
+    }
+}
+
+__global__ void compound_kernel(const float2* __restrict__ image, int S, int npix, int mode,
+                                float* __restrict__ inten) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix) return;
+    if (mode == KK_COMPOUND_COHERENT) {
+        float2 a = make_float2(0.f, 0.f);
+        for (int s = 0; s < S; ++s) {
+            const float2 v = image[(size_t)s * npix + i];
+            a.x += v.x;
+            a.y += v.y;
+        }
+        inten[i] = a.x * a.x + a.y * a.y;
+    } else {
+        float a = 0.f;
+        for (int s = 0; s < S; ++s) {
+            const float2 v = image[(size_t)s * npix + i];
+            a += v.x * v.x + v.y * v.y;
+        }
+        inten[i] = a;
+    }
+}
+
+template <int CAP>
+hipError_t launch_kk(const float2* rec, const int32_t* plan_dev, float2* image, int blocks, int n, int m, int t,
+                     hipStream_t st) {
+    constexpr int PB = pairs_per_batch(CAP);
+    hipLaunchKernelGGL((kk_gather_kernel<CAP, PB>), dim3(blocks), dim3(kThreads), 0, st, rec, plan_dev, image, n,
+                       m, t);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace kk
+
+extern "C" {
+
+int32_t kk_compound(const float* image, int32_t S, int32_t X, int32_t Z, int32_t mode, float* intensity,
+                    void* stream) {
+    if (!image || !intensity) return KK_E_NULL;
+    if (S < 1 || X < 1 || Z < 1 || (mode != KK_COMPOUND_COHERENT && mode != KK_COMPOUND_INCOHERENT))
+        return KK_E_ARG;
+    const int64_t npix = (int64_t)X * Z;
+    if (npix > 0x7fffffff) return KK_E_ARG;
+    const int blocks = (int)((npix + 255) / 256);
+    hipLaunchKernelGGL(kk::compound_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float2*>(image), S, (int)npix, mode, intensity);
+    return hipGetLastError() == hipSuccess ? KK_OK : KK_E_HIP;
+}
+
+int32_t kk_beamform(const float* rf_theta, int32_t N, int32_t M, int32_t T, const void* plan_host,
+                    const void* plan_dev, size_t plan_bytes, float* image, float* intensity, int32_t mode,
+                    void* stream) {
+    using namespace kk;
+    if (!rf_theta || !plan_host || !plan_dev || !image) return KK_E_NULL;
+    const int32_t* h = static_cast<const int32_t*>(plan_host);
+    if (plan_bytes < (size_t)PW_HEADER_WORDS * 4 || h[PW_MAGIC] != kPlanMagic || h[PW_KIND] != kPlanKindKK ||
+        (size_t)h[PW_TOTAL] * 4 > plan_bytes || h[PW_PB] != pairs_per_batch(h[PW_CAP]))
+        return KK_E_WORKSPACE;
+    if (h[PW_N] != N || h[PW_M] != M || h[PW_T] != T || N < 1 || M < 1 || T < 1) return KK_E_ARG;
+    if (intensity && mode != KK_COMPOUND_COHERENT && mode != KK_COMPOUND_INCOHERENT) return KK_E_ARG;
+    const int64_t blocks = (int64_t)h[PW_NXT] * h[PW_NZT] * h[PW_S];
+    if (blocks < 1 || blocks > 0x7fffffff) return KK_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const float2* rec = reinterpret_cast<const float2*>(rf_theta);
+    const int32_t* pd = static_cast<const int32_t*>(plan_dev);
+    float2* img = reinterpret_cast<float2*>(image);
+    hipError_t e;
+    switch (h[PW_CAP]) {
+        case 64: e = launch_kk<64>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 128: e = launch_kk<128>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 192: e = launch_kk<192>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 256: e = launch_kk<256>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 320: e = launch_kk<320>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 384: e = launch_kk<384>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 448: e = launch_kk<448>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        case 512: e = launch_kk<512>(rec, pd, img, (int)blocks, N, M, T, st); break;
+        default: return KK_E_WORKSPACE;
+    }
+    if (e != hipSuccess) return KK_E_HIP;
+    if (intensity) return kk_compound(image, h[PW_S], h[PW_X], h[PW_Z], mode, intensity, stream);
+    return KK_OK;
+}
+
+}  // extern "C"
