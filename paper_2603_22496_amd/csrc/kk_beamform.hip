@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "../../include/kk.h"
+#include "kk_internal.h"
 #include "kk_plan.h"
 
 namespace kk {
@@ -53,46 +54,51 @@ __device__ __forceinline__ int xcd_remap(int id, int total) {
     return xcd * base + (xcd < rem ? xcd : rem) + k;
 }
 
-template <int CAP, int PB>
+template <int CAP, int PB, bool DAS>
 struct Lds {
     static constexpr int kWinBytes = 2 * PB * CAP * 16;
     static constexpr int kABytes = 2 * PB * 64 * 4;
     static constexpr int kBBytes = 2 * PB * 16 * 4;
-    static constexpr int kBytes = kWinBytes + kABytes + kBBytes;
+    static constexpr int kCBytes = DAS ? 2 * 2 * 1024 * 4 : 0;  // DAS: two elements per buffer
+    static constexpr int kBytes = kWinBytes + kABytes + kBBytes + kCBytes;
     static_assert(kBytes <= 160 * 1024, "LDS budget");
     static_assert(kWinBytes / 16 < 65536, "entry index must fit 16 bits");
     static_assert(3 * 256 * kRows * 8 <= kBytes, "reduction scratch fits the buffers");
 };
 
-// Window rows staged by one wave: lanes cover 64 consecutive entries per row.
+// Global loads of one batch, held in registers while the previous batch is gathered.
 template <int CAP>
 struct Prefetch {
-    F4a8 v[2][CAP / 64];  // (R[n], R[n+1]) per row, up to two slots per wave
+    F4a8 v[2][CAP / 64];  // (R[n], R[n+1]) per row of 64 entries, up to two slots per wave
     int32_t a[2];
     int32_t b[2];
+    int32_t c[2];         // DAS: receive delay of pixel (wave row, lane) for two elements
 };
 
-template <int CAP, int PB>
+struct PlanView {
+    int T, P, N, xpad, zpad, xt, zt, tile, off_rec, off_a, off_b, off_lo, off_c, off_tx;
+};
+
+template <int CAP, int PB, bool DAS>
 __device__ __forceinline__ void load_batch(Prefetch<CAP>& pf, const float2* __restrict__ rec,
-                                           const int32_t* __restrict__ plan, int tile, int q0, int nb,
-                                           int wave, int lane, int T, int P, int xpad, int zpad, int xt,
-                                           int zt, int off_rec, int off_a, int off_b, int off_lo) {
+                                           const int32_t* __restrict__ plan, const PlanView& pv, int q0, int nb,
+                                           int wave, int lane) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int j = wave + u * kWaves;
         if (j < nb) {
             const int q = q0 + j;
-            const int lo = plan[off_lo + tile * P + q];
-            const float2* rp = rec + (size_t)plan[off_rec + q] * T;
+            const int lo = plan[pv.off_lo + pv.tile * pv.P + q];
+            const float2* rp = rec + (size_t)plan[pv.off_rec + q] * pv.T;
 #pragma unroll
             for (int r = 0; r < CAP / 64; ++r) {
                 const int n = lo + r * 64 + lane;
                 F4a8 v;
-                if ((unsigned)n < (unsigned)(T - 1)) {
+                if ((unsigned)n < (unsigned)(pv.T - 1)) {
                     v = *reinterpret_cast<const F4a8*>(rp + n);
                 } else {
-                    float2 a = ((unsigned)n < (unsigned)T) ? rp[n] : make_float2(0.f, 0.f);
-                    float2 b = ((unsigned)(n + 1) < (unsigned)T) ? rp[n + 1] : make_float2(0.f, 0.f);
+                    float2 a = ((unsigned)n < (unsigned)pv.T) ? rp[n] : make_float2(0.f, 0.f);
+                    float2 b = ((unsigned)(n + 1) < (unsigned)pv.T) ? rp[n + 1] : make_float2(0.f, 0.f);
                     v.x = a.x;
                     v.y = a.y;
                     v.z = b.x;
@@ -100,17 +106,28 @@ __device__ __forceinline__ void load_batch(Prefetch<CAP>& pf, const float2* __re
                 }
                 pf.v[u][r] = v;
             }
-            pf.a[u] = plan[off_a + q * xpad + xt * 64 + lane];
-            pf.b[u] = lane < 16 ? plan[off_b + q * zpad + zt * 16 + lane] : 0;
+            const int row = DAS ? plan[pv.off_tx + q] : q;  // DAS: transmit delays are per transmit
+            pf.a[u] = plan[pv.off_a + row * pv.xpad + pv.xt * 64 + lane];
+            pf.b[u] = lane < 16 ? plan[pv.off_b + row * pv.zpad + pv.zt * 16 + lane] : 0;
         }
+    }
+    if constexpr (DAS) {
+        // receive delays of the (at most two) elements of this batch, pixel (row = wave, lane)
+        const int l0 = q0 / pv.N;
+        const int nl = (q0 + nb - 1) / pv.N - l0 + 1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (u < nl)
+                pf.c[u] = plan[pv.off_c + ((size_t)(l0 + u) * pv.zpad + pv.zt * 16 + wave) * pv.xpad + pv.xt * 64 +
+                               lane];
     }
 }
 
-template <int CAP, int PB>
+template <int CAP, int PB, bool DAS>
 __device__ __forceinline__ void store_batch(const Prefetch<CAP>& pf, unsigned char* lds, int buf, int nb,
-                                            const int32_t* __restrict__ plan, int tile, int q0, int wave,
-                                            int lane, int P, int off_lo) {
-    using L = Lds<CAP, PB>;
+                                            const int32_t* __restrict__ plan, const PlanView& pv, int q0,
+                                            int wave, int lane) {
+    using L = Lds<CAP, PB, DAS>;
     float4* win = reinterpret_cast<float4*>(lds);
     int32_t* aslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes);
     int32_t* bslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes + L::kABytes);
@@ -120,39 +137,69 @@ __device__ __forceinline__ void store_batch(const Prefetch<CAP>& pf, unsigned ch
         const int j = wave + u * kWaves;
         if (j < nb) {
             const int slot = buf * PB + j;
-            const int lo = plan[off_lo + tile * P + q0 + j];
+            const int lo = plan[pv.off_lo + pv.tile * pv.P + q0 + j];
 #pragma unroll
             for (int r = 0; r < CAP / 64; ++r) {
                 const F4a8 v = pf.v[u][r];
                 win[slot * CAP + r * 64 + lane] =
                     make_float4(v.x, v.y, (v.z - v.x) * scale, (v.w - v.y) * scale);
             }
-            // integer part of (A + B) becomes the entry index of the sample inside LDS
+            // integer part of the delay becomes the entry index of the sample inside LDS
             aslot[slot * 64 + lane] = (int32_t)((uint32_t)pf.a[u] + ((uint32_t)(slot * CAP - lo) << 16));
             if (lane < 16) bslot[slot * 16 + lane] = pf.b[u];
         }
     }
+    if constexpr (DAS) {
+        int32_t* cslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes + L::kABytes + L::kBBytes);
+        const int l0 = q0 / pv.N;
+        const int nl = (q0 + nb - 1) / pv.N - l0 + 1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (u < nl) cslot[((buf * 2 + u) * 16 + wave) * 64 + lane] = pf.c[u];
+    }
 }
 
-template <int CAP, int PB>
-__global__ __launch_bounds__(kThreads) void kk_gather_kernel(const float2* __restrict__ rec,
-                                                             const int32_t* __restrict__ plan,
-                                                             float2* __restrict__ image, int n_arg,
-                                                             int m_arg, int t_arg) {
-    using L = Lds<CAP, PB>;
+// pairs of the next batch: at most PB, and for DAS at most two elements (l) per batch
+template <int PB, bool DAS>
+__device__ __forceinline__ int batch_size(int q, int p_end, int N) {
+    int nb = min(PB, p_end - q);
+    if (DAS) nb = min(nb, (q / N + 2) * N - q);
+    return nb;
+}
+
+template <int CAP, int PB, bool DAS>
+__global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restrict__ rec,
+                                                          const int32_t* __restrict__ plan,
+                                                          float2* __restrict__ image, int n_arg, int m_arg,
+                                                          int t_arg) {
+    using L = Lds<CAP, PB, DAS>;
     __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
     // a device plan that does not describe this call is ignored (uniform early exit)
-    if (plan[PW_MAGIC] != kPlanMagic || plan[PW_KIND] != kPlanKindKK || plan[PW_N] != n_arg ||
-        plan[PW_M] != m_arg || plan[PW_T] != t_arg || plan[PW_CAP] != CAP || plan[PW_PB] != PB)
+    if (plan[PW_MAGIC] != kPlanMagic || plan[PW_KIND] != (DAS ? kPlanKindDAS : kPlanKindKK) ||
+        plan[PW_N] != n_arg || plan[PW_M] != m_arg || plan[PW_T] != t_arg || plan[PW_CAP] != CAP ||
+        plan[PW_PB] != PB)
         return;
-    const int T = plan[PW_T], P = plan[PW_P], S = plan[PW_S], X = plan[PW_X], Z = plan[PW_Z];
-    const int nxt = plan[PW_NXT], nzt = plan[PW_NZT], xpad = plan[PW_XPAD], zpad = plan[PW_ZPAD];
-    const int off_set = plan[PW_OFF_SET], off_rec = plan[PW_OFF_REC], off_a = plan[PW_OFF_A],
-              off_b = plan[PW_OFF_B], off_lo = plan[PW_OFF_LO];
+    PlanView pv;
+    pv.T = plan[PW_T];
+    pv.P = plan[PW_P];
+    pv.N = plan[PW_N];
+    const int S = plan[PW_S], X = plan[PW_X], Z = plan[PW_Z];
+    const int nxt = plan[PW_NXT], nzt = plan[PW_NZT];
+    pv.xpad = plan[PW_XPAD];
+    pv.zpad = plan[PW_ZPAD];
+    pv.off_rec = plan[PW_OFF_REC];
+    pv.off_a = plan[PW_OFF_A];
+    pv.off_b = plan[PW_OFF_B];
+    pv.off_lo = plan[PW_OFF_LO];
+    pv.off_c = plan[PW_OFF_C];
+    pv.off_tx = plan[PW_OFF_TX];
+    const int off_set = plan[PW_OFF_SET];
     const int ntiles = nxt * nzt;
     const int r = xcd_remap(blockIdx.x, ntiles * S);
-    const int s = r / ntiles, tile = r - s * ntiles;
-    const int zt = tile / nxt, xt = tile - zt * nxt;
+    const int s = r / ntiles;
+    pv.tile = r - s * ntiles;
+    pv.zt = pv.tile / nxt;
+    pv.xt = pv.tile - pv.zt * nxt;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int group = wave >> 2, quarter = wave & 3;
@@ -165,30 +212,41 @@ __global__ __launch_bounds__(kThreads) void kk_gather_kernel(const float2* __res
     const float4* win = reinterpret_cast<const float4*>(lds);
     const int32_t* aslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes);
     const int32_t* bslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes + L::kABytes);
+    const int32_t* cslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes + L::kABytes + L::kBBytes);
 
     Prefetch<CAP> pf;
     int q0 = p_begin;
-    int nb = min(PB, p_end - q0);
-    load_batch<CAP, PB>(pf, rec, plan, tile, q0, nb, wave, lane, T, P, xpad, zpad, xt, zt, off_rec, off_a, off_b,
-                        off_lo);
-    store_batch<CAP, PB>(pf, lds, 0, nb, plan, tile, q0, wave, lane, P, off_lo);
+    int nb = batch_size<PB, DAS>(q0, p_end, pv.N);
+    load_batch<CAP, PB, DAS>(pf, rec, plan, pv, q0, nb, wave, lane);
+    store_batch<CAP, PB, DAS>(pf, lds, 0, nb, plan, pv, q0, wave, lane);
     __syncthreads();
     int buf = 0;
     constexpr int kPerGroup = PB / kGroups;
     while (true) {
         const int q1 = q0 + nb;
-        const int nb1 = min(PB, p_end - q1);
-        if (nb1 > 0)
-            load_batch<CAP, PB>(pf, rec, plan, tile, q1, nb1, wave, lane, T, P, xpad, zpad, xt, zt, off_rec, off_a,
-                                off_b, off_lo);
+        const int nb1 = q1 < p_end ? batch_size<PB, DAS>(q1, p_end, pv.N) : 0;
+        if (nb1 > 0) load_batch<CAP, PB, DAS>(pf, rec, plan, pv, q1, nb1, wave, lane);
         // gather: this group's contiguous share of the batch
         const int j0 = group * kPerGroup;
         const int j1 = min(j0 + kPerGroup, nb);
+        uint32_t cq[kRows] = {0u, 0u, 0u, 0u};
+        int cur_u = -1;
         for (int j = j0; j < j1; ++j) {
             const int slot = buf * PB + j;
             const uint32_t a = (uint32_t)aslot[slot * 64 + lane];
             const int4 b = *reinterpret_cast<const int4*>(&bslot[slot * 16 + quarter * 4]);
-            const uint32_t bq[4] = {(uint32_t)b.x, (uint32_t)b.y, (uint32_t)b.z, (uint32_t)b.w};
+            uint32_t bq[kRows] = {(uint32_t)b.x, (uint32_t)b.y, (uint32_t)b.z, (uint32_t)b.w};
+            if constexpr (DAS) {
+                const int u = (q0 + j) / pv.N - q0 / pv.N;
+                if (u != cur_u) {
+                    cur_u = u;
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k)
+                        cq[k] = (uint32_t)cslot[((buf * 2 + u) * 16 + quarter * kRows + k) * 64 + lane];
+                }
+#pragma unroll
+                for (int k = 0; k < kRows; ++k) bq[k] += cq[k];
+            }
 #pragma unroll
             for (int k = 0; k < kRows; ++k) {
                 const uint32_t q = a + bq[k];
@@ -202,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void kk_gather_kernel(const float2* __res
             }
         }
         if (nb1 <= 0) break;
-        store_batch<CAP, PB>(pf, lds, buf ^ 1, nb1, plan, tile, q1, wave, lane, P, off_lo);
+        store_batch<CAP, PB, DAS>(pf, lds, buf ^ 1, nb1, plan, pv, q1, wave, lane);
         __syncthreads();
         buf ^= 1;
         q0 = q1;
@@ -218,8 +276,8 @@ __global__ __launch_bounds__(kThreads) void kk_gather_kernel(const float2* __res
     }
     __syncthreads();
     if (group == 0) {
-        const int x = xt * 64 + lane;
-        const int z0 = zt * 16 + quarter * kRows;
+        const int x = pv.xt * 64 + lane;
+        const int z0 = pv.zt * 16 + quarter * kRows;
         if (x < X) {
             float2* out = image + ((size_t)s * X + x) * Z;
 #pragma unroll
@@ -259,16 +317,40 @@ __global__ void compound_kernel(const float2* __restrict__ image, int S, int npi
     }
 }
 
-template <int CAP>
-hipError_t launch_kk(const float2* rec, const int32_t* plan_dev, float2* image, int blocks, int n, int m, int t,
-                     hipStream_t st) {
+template <int CAP, bool DAS>
+hipError_t launch_gather(const float2* rec, const int32_t* plan_dev, float2* image, int blocks, int n, int m, int t,
+                         hipStream_t st) {
     constexpr int PB = pairs_per_batch(CAP);
-    hipLaunchKernelGGL((kk_gather_kernel<CAP, PB>), dim3(blocks), dim3(kThreads), 0, st, rec, plan_dev, image, n,
+    hipLaunchKernelGGL((gather_kernel<CAP, PB, DAS>), dim3(blocks), dim3(kThreads), 0, st, rec, plan_dev, image, n,
                        m, t);
     return hipGetLastError();
 }
 
+template <bool DAS>
+hipError_t dispatch_gather(const float2* rec, const int32_t* h, const int32_t* pd, float2* img, hipStream_t st) {
+    const int64_t blocks = (int64_t)h[PW_NXT] * h[PW_NZT] * h[PW_S];
+    if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const int b = (int)blocks, n = h[PW_N], m = h[PW_M], t = h[PW_T];
+    switch (h[PW_CAP]) {
+        case 64: return launch_gather<64, DAS>(rec, pd, img, b, n, m, t, st);
+        case 128: return launch_gather<128, DAS>(rec, pd, img, b, n, m, t, st);
+        case 192: return launch_gather<192, DAS>(rec, pd, img, b, n, m, t, st);
+        case 256: return launch_gather<256, DAS>(rec, pd, img, b, n, m, t, st);
+        case 320: return launch_gather<320, DAS>(rec, pd, img, b, n, m, t, st);
+        case 384: return launch_gather<384, DAS>(rec, pd, img, b, n, m, t, st);
+        case 448: return launch_gather<448, DAS>(rec, pd, img, b, n, m, t, st);
+        case 512: return launch_gather<512, DAS>(rec, pd, img, b, n, m, t, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_das_gather(const float2* rfa, const int32_t* plan_host, const int32_t* plan_dev, float2* image,
+                             hipStream_t st) {
+    return dispatch_gather<true>(rfa, plan_host, plan_dev, image, st);
+}
+
 }  // namespace kk
 
 extern "C" {
@@ -297,24 +379,10 @@ int32_t kk_beamform(const float* rf_theta, int32_t N, int32_t M, int32_t T, cons
         return KK_E_WORKSPACE;
     if (h[PW_N] != N || h[PW_M] != M || h[PW_T] != T || N < 1 || M < 1 || T < 1) return KK_E_ARG;
     if (intensity && mode != KK_COMPOUND_COHERENT && mode != KK_COMPOUND_INCOHERENT) return KK_E_ARG;
-    const int64_t blocks = (int64_t)h[PW_NXT] * h[PW_NZT] * h[PW_S];
-    if (blocks < 1 || blocks > 0x7fffffff) return KK_E_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    const float2* rec = reinterpret_cast<const float2*>(rf_theta);
-    const int32_t* pd = static_cast<const int32_t*>(plan_dev);
-    float2* img = reinterpret_cast<float2*>(image);
-    hipError_t e;
-    switch (h[PW_CAP]) {
-        case 64: e = launch_kk<64>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 128: e = launch_kk<128>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 192: e = launch_kk<192>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 256: e = launch_kk<256>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 320: e = launch_kk<320>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 384: e = launch_kk<384>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 448: e = launch_kk<448>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        case 512: e = launch_kk<512>(rec, pd, img, (int)blocks, N, M, T, st); break;
-        default: return KK_E_WORKSPACE;
-    }
+    const hipError_t e = dispatch_gather<false>(reinterpret_cast<const float2*>(rf_theta), h,
+                                                static_cast<const int32_t*>(plan_dev), reinterpret_cast<float2*>(image),
+                                                st);
     if (e != hipSuccess) return KK_E_HIP;
     if (intensity) return kk_compound(image, h[PW_S], h[PW_X], h[PW_Z], mode, intensity, stream);
     return KK_OK;

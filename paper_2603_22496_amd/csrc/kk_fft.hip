@@ -1,0 +1,376 @@
+// Power-of-two FFTs for gfx950 (FP32), used by the decomposition (Sec. II-F: analytic signal by
+// a temporal FFT with negative frequencies zeroed, shear by the Fourier shift theorem) and by
+// the DAS comparator.
+//
+// Stockham autosort in LDS with radix-16 passes (register-resident 16-point DFTs built from
+// radix-2/4 stages with exact internal constants) and one radix-2/4/8 pass for the remainder,
+// 256 threads per transform.  The first pass reads global memory directly (coalesced), every
+// later pass goes through one LDS round trip; twiddles come from an FP64-evaluated table held
+// in LDS.  Forward transforms take two real int16 records per workgroup as the real and
+// imaginary parts of one complex sequence and unpack them straight into the two masked
+// analytic spectra: for 0 < k < n/2, A[k] = Z[k] + conj(Z[n-k]) and
+// B[k] = -i (Z[k] - conj(Z[n-k])) (the x2 of the analytic mask absorbs the 1/2 of the unpack);
+// A[0] = Re Z[0], B[0] = Im Z[0], likewise at k = n/2.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kk_internal.h"
+
+namespace kk {
+namespace {
+
+constexpr int kFftThreads = 256;
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {  // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by exp(-i pi/2) = -i (forward) or exp(+i pi/2) = +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 a) {
+    return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        const float2 s0 = cadd(v[0], v[2]), d0 = csub(v[0], v[2]);
+        const float2 s1 = cadd(v[1], v[3]), d1 = rot90<INV>(csub(v[1], v[3]));
+        v[0] = cadd(s0, s1);
+        v[2] = csub(s0, s1);
+        v[1] = cadd(d0, d1);
+        v[3] = csub(d0, d1);
+    }
+};
+
+template <bool INV>
+struct Dft<8, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        constexpr float c = 0.70710678118654752440f;
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, INV>::run(e);
+        Dft<4, INV>::run(o);
+        float2 t[4];
+        t[0] = o[0];
+        t[1] = INV ? make_float2(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                   : make_float2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+        t[2] = rot90<INV>(o[2]);
+        t[3] = INV ? make_float2(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                   : make_float2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], t[k]);
+            v[k + 4] = csub(e[k], t[k]);
+        }
+    }
+};
+
+template <bool INV>
+struct Dft<16, INV> {
+    __device__ __forceinline__ static void run(float2* v) {
+        // cos and sin of pi k / 8, k = 0..7
+        constexpr float C[8] = {1.0f, 0.92387953251128675613f, 0.70710678118654752440f, 0.38268343236508977173f,
+                                0.0f, -0.38268343236508977173f, -0.70710678118654752440f, -0.92387953251128675613f};
+        constexpr float S[8] = {0.0f, 0.38268343236508977173f, 0.70710678118654752440f, 0.92387953251128675613f,
+                                1.0f, 0.92387953251128675613f, 0.70710678118654752440f, 0.38268343236508977173f};
+        float2 e[8], o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            e[k] = v[2 * k];
+            o[k] = v[2 * k + 1];
+        }
+        Dft<8, INV>::run(e);
+        Dft<8, INV>::run(o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float2 t;
+            if (k == 0) {
+                t = o[0];
+            } else if (k == 4) {
+                t = rot90<INV>(o[4]);
+            } else {
+                t = cmul(o[k], make_float2(C[k], INV ? S[k] : -S[k]));
+            }
+            v[k] = cadd(e[k], t);
+            v[k + 8] = csub(e[k], t);
+        }
+    }
+};
+
+template <int LOG2N>
+struct FftPlan {
+    static constexpr int N = 1 << LOG2N;
+    static constexpr int P16 = LOG2N / 4;
+    static constexpr int REM = 1 << (LOG2N % 4);
+    static constexpr int NPASS = P16 + (REM > 1 ? 1 : 0);
+    static constexpr int radix(int p) { return p < P16 ? 16 : REM; }
+    static constexpr int ns(int p) { return p == 0 ? 1 : ns(p - 1) * radix(p - 1); }
+};
+
+// twiddles of butterfly b in a pass with NS already-combined points: v[r] *= W_{NS R}^{r k}
+template <int N, int R, int NS, bool INV>
+__device__ __forceinline__ void twiddle(float2* v, int b, const float2* tw) {
+    if constexpr (NS > 1) {
+        const int k = b % NS;
+        constexpr int step = N / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            const float2 w = tw[r * k * step];
+            v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+        }
+    }
+}
+
+template <int N, int R, int NS>
+__device__ __forceinline__ int out_index(int b, int r) {
+    const int k = b % NS;
+    return (b / NS) * NS * R + k + r * NS;
+}
+
+// one Stockham pass LDS -> LDS (in place: all reads, barrier, all writes, barrier)
+template <int N, int R, int NS, bool INV>
+__device__ __forceinline__ void pass_lds(float2* data, const float2* tw, int tid) {
+    constexpr int NB = N / R;
+    constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+    float2 v[PER][R];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int b = tid + p * kFftThreads;
+        if (b < NB) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[p][r] = data[b + r * NB];
+            twiddle<N, R, NS, INV>(v[p], b, tw);
+            Dft<R, INV>::run(v[p]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int b = tid + p * kFftThreads;
+        if (b < NB) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) data[out_index<N, R, NS>(b, r)] = v[p][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int LOG2N, int P, bool INV>
+__device__ __forceinline__ void middle_passes(float2* data, const float2* tw, int tid) {
+    using F = FftPlan<LOG2N>;
+    if constexpr (P < F::NPASS - 1) {
+        pass_lds<F::N, F::radix(P), F::ns(P), INV>(data, tw, tid);
+        middle_passes<LOG2N, P + 1, INV>(data, tw, tid);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void load_table(float2* tw_s, const float2* __restrict__ tw, int tid) {
+    for (int m = tid; m < N; m += kFftThreads) tw_s[m] = tw[m];
+}
+
+template <int LOG2N, bool BLOCKED>
+__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
+                                                                  int T, const float2* __restrict__ tw,
+                                                                  float2* __restrict__ out, int L, int ncol,
+                                                                  int kpad) {
+    using F = FftPlan<LOG2N>;
+    constexpr int N = F::N;
+    __shared__ float2 data[N];
+    __shared__ float2 tw_s[N];
+    const int tid = threadIdx.x;
+    const int t0 = 2 * blockIdx.x, t1 = t0 + 1;
+    const bool has1 = t1 < ntraces;
+    load_table<N>(tw_s, tw, tid);
+    const int16_t* a = rf + (size_t)t0 * T;
+    const int16_t* b = rf + (size_t)(has1 ? t1 : t0) * T;
+    {  // first pass straight from the int16 records (zero beyond T)
+        constexpr int R = F::radix(0);
+        constexpr int NB = N / R;
+        constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int bb = tid + p * kFftThreads;
+            if (bb < NB) {
+                float2 v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int n = bb + r * NB;
+                    v[r] = n < T ? make_float2((float)a[n], has1 ? (float)b[n] : 0.0f) : make_float2(0.f, 0.f);
+                }
+                Dft<R, false>::run(v);
+#pragma unroll
+                for (int r = 0; r < R; ++r) data[out_index<N, R, 1>(bb, r)] = v[r];
+            }
+        }
+        __syncthreads();
+    }
+    middle_passes<LOG2N, 1, false>(data, tw_s, tid);
+    pass_lds<N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, tw_s, tid);
+    // unpack the two real spectra with the analytic mask
+    const int i0 = t0 / L, l0 = t0 - i0 * L, i1 = t1 / L, l1 = t1 - i1 * L;
+    for (int k = tid; k <= N / 2; k += kFftThreads) {
+        const float2 zk = data[k];
+        const float2 zm = data[(N - k) & (N - 1)];
+        float2 A, B;
+        if (k == 0 || k == N / 2) {
+            A = make_float2(zk.x, 0.f);
+            B = make_float2(zk.y, 0.f);
+        } else {
+            A = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
+            B = make_float2(d.y, -d.x);
+        }
+        if (BLOCKED) {
+            const size_t kb = (size_t)(k >> 3), kk = (size_t)(k & 7);
+            out[(((kb * ncol + i0) * L + l0) << 3) + kk] = A;
+            if (has1) out[(((kb * ncol + i1) * L + l1) << 3) + kk] = B;
+        } else {
+            out[(size_t)t0 * kpad + k] = A;
+            if (has1) out[(size_t)t1 * kpad + k] = B;
+        }
+    }
+}
+
+template <int LOG2N>
+__global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* __restrict__ in, int kpad,
+                                                                  const float2* __restrict__ tw,
+                                                                  float2* __restrict__ out, int T) {
+    using F = FftPlan<LOG2N>;
+    constexpr int N = F::N;
+    constexpr int K = N / 2 + 1;
+    __shared__ float2 data[N];
+    __shared__ float2 tw_s[N];
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x;
+    load_table<N>(tw_s, tw, tid);
+    const float2* y = in + (size_t)t * kpad;
+    {  // first pass from the K non-negative bins (negative bins are zero)
+        constexpr int R = F::radix(0);
+        constexpr int NB = N / R;
+        constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int bb = tid + p * kFftThreads;
+            if (bb < NB) {
+                float2 v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = bb + r * NB;
+                    v[r] = k < K ? y[k] : make_float2(0.f, 0.f);
+                }
+                Dft<R, true>::run(v);
+#pragma unroll
+                for (int r = 0; r < R; ++r) data[out_index<N, R, 1>(bb, r)] = v[r];
+            }
+        }
+        __syncthreads();
+    }
+    middle_passes<LOG2N, 1, true>(data, tw_s, tid);
+    {  // last pass straight to the output record, scaled by 1/N
+        constexpr int P = F::NPASS - 1;
+        constexpr int R = F::radix(P);
+        constexpr int NS = F::ns(P);
+        constexpr int NB = N / R;
+        constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+        constexpr float scale = 1.0f / (float)N;
+        float2* o = out + (size_t)t * T;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int bb = tid + p * kFftThreads;
+            if (bb < NB) {
+                float2 v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = data[bb + r * NB];
+                twiddle<N, R, NS, true>(v, bb, tw_s);
+                Dft<R, true>::run(v);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int n = out_index<N, R, NS>(bb, r);
+                    if (n < T) o[n] = make_float2(v[r].x * scale, v[r].y * scale);
+                }
+            }
+        }
+    }
+}
+
+__global__ void twiddle_kernel(float2* tw, int log2n) {
+    const int n = 1 << log2n;
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    tw[m] = make_float2((float)c, (float)(-s));
+}
+
+template <int LOG2N>
+hipError_t fwd(const int16_t* rf, int ntraces, int T, const float2* tw, float2* out, bool blocked, int L, int ncol,
+               int kpad, hipStream_t st) {
+    const int blocks = (ntraces + 1) / 2;
+    if (blocked)
+        hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces, T,
+                           tw, out, L, ncol, kpad);
+    else
+        hipLaunchKernelGGL((fft_forward_kernel<LOG2N, false>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces,
+                           T, tw, out, L, ncol, kpad);
+    return hipGetLastError();
+}
+
+template <int LOG2N>
+hipError_t inv(const float2* in, int ntraces, int kpad, const float2* tw, float2* out, int T, hipStream_t st) {
+    hipLaunchKernelGGL((fft_inverse_kernel<LOG2N>), dim3(ntraces), dim3(kFftThreads), 0, st, in, kpad, tw, out, T);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_twiddles(float2* tw, int log2n, hipStream_t st) {
+    const int n = 1 << log2n;
+    hipLaunchKernelGGL(twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tw, log2n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, const float2* tw, float2* out,
+                              bool blocked, int L, int ncol, int kpad, hipStream_t st) {
+    switch (log2n) {
+        case 8: return fwd<8>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        case 9: return fwd<9>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        case 10: return fwd<10>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        case 11: return fwd<11>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        case 12: return fwd<12>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        case 13: return fwd<13>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fft_inverse(const float2* in, int ntraces, int kpad, int log2n, const float2* tw, float2* out,
+                              int T, hipStream_t st) {
+    switch (log2n) {
+        case 8: return inv<8>(in, ntraces, kpad, tw, out, T, st);
+        case 9: return inv<9>(in, ntraces, kpad, tw, out, T, st);
+        case 10: return inv<10>(in, ntraces, kpad, tw, out, T, st);
+        case 11: return inv<11>(in, ntraces, kpad, tw, out, T, st);
+        case 12: return inv<12>(in, ntraces, kpad, tw, out, T, st);
+        case 13: return inv<13>(in, ntraces, kpad, tw, out, T, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace kk

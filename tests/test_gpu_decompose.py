@@ -1,0 +1,188 @@
+"""GPU parity of kk_decompose (Eq. 3 via Sec. II-F), das_beamform (Eq. 4) and the end-to-end
+KK frame (Eq. 3 + Eq. 5) against the FP64 oracle on the same int16 channel data.
+
+Bars: RF_theta and DAS/KK images within rel-L2 1e-5 of the FP64 oracle (the FP32 parity
+path; FFT + contraction + inverse FFT + gather errors are each ~1e-7..1e-6).
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2603_22496_amd import configs as C
+from paper_2603_22496_amd.phantom import Acquisition, make_dataset, seeded_points
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def kk():
+    import torch
+    from paper_2603_22496_amd import kk as K
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    K.lib()
+    return K
+
+
+def _decompose_gpu(K, rf, L, T, shift, tpad):
+    import torch
+    g = K.geom(L, T, 0.3e-3, 1540.0, 20e6, 0.0)
+    out = K.decompose(K.to_device(rf), g, K.to_device(np.ascontiguousarray(shift, dtype=np.int32)),
+                      shift.shape[0], tpad)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_tiny_rf_theta(kk):
+    w = C.TINY
+    ds = C.tiny_dataset(0)
+    su = kk.make_setup(w)
+    got = _decompose_gpu(kk, ds.rf, w.L, w.T, su.luts["shift"], su.tpad)
+    ref = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+
+
+@pytest.mark.parametrize("N,L,T,M,tpad,seed", [
+    (3, 5, 200, 4, 256, 1),       # odd trace count (one unpaired record), tiny FFT
+    (5, 7, 333, 17, 512, 2),      # two row tiles of receive angles
+    (33, 6, 1000, 3, 1024, 3),    # two column tiles of transmits
+    (2, 9, 1024, 2, 1024, 4),     # record fills the whole FFT (no padding)
+    (2, 4, 3000, 3, 4096, 5),
+    (1, 3, 5000, 2, 8192, 6),
+])
+def test_shapes_and_random_shifts(kk, N, L, T, M, tpad, seed):
+    rng = np.random.default_rng(seed)
+    rf = rng.integers(-32768, 32767, size=(N, L, T)).astype(np.int16)
+    shift = rng.integers(-2 ** 31, 2 ** 31 - 1, size=(M, L)).astype(np.int32)
+    shift[0] = 0                                   # a broadside row
+    if M > 1:
+        shift[1] = (np.arange(L) * 3) << 22        # integer advances
+    got = _decompose_gpu(kk, rf, L, T, shift, tpad)
+    ref = O.decompose(rf, shift, tpad)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+    for o in range(M):
+        assert _rel(got[:, o], ref[:, o]) <= 3 * TOL
+
+
+def test_vernier_rf_theta(kk):
+    w = C.VERNIER
+    ds = C.speckle_dataset(w, seed=2, n_scat=20000)
+    su = kk.make_setup(w)
+    got = _decompose_gpu(kk, ds.rf, w.L, w.T, su.luts["shift"], su.tpad)
+    ref = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+
+
+def test_full_bank_rf_theta_sampled_angles(kk):
+    w = C.FULL
+    ds = C.speckle_dataset(C.VERNIER, seed=2, n_scat=20000)
+    su = kk.make_setup(w)
+    got = _decompose_gpu(kk, ds.rf, w.L, w.T, su.luts["shift"], su.tpad)
+    pick = [0, 1, 17, 63, 64, 100, 126, 127]
+    ref = O.decompose(ds.rf, su.luts["shift"][pick], su.tpad)
+    assert _rel(got[:, pick], ref) <= TOL, _rel(got[:, pick], ref)
+
+
+def _frame(K, su, rf):
+    import torch
+    rt = K.decompose(K.to_device(rf), su.geom, K.to_device(su.luts["shift"]), su.M, su.tpad)
+    img = K.beamform(rt, su.plan, K.to_device(su.plan))
+    torch.cuda.synchronize()
+    return img.cpu().numpy()
+
+
+@pytest.mark.parametrize("scheme,M,jl", [
+    (C.SCHEME_FULL_UNIFORM, 16, (0,)),
+    (C.SCHEME_SHIFTED, 7, (0, 1, 2)),
+    (C.SCHEME_CONFOCAL, 9, (0,)),
+])
+def test_tiny_end_to_end_image(kk, scheme, M, jl):
+    w = C.TINY
+    ds = C.tiny_dataset(7)
+    su = kk.make_setup(w, scheme=scheme, M=M, j_list=jl)
+    got = _frame(kk, su, ds.rf)
+    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+
+
+def test_vernier_end_to_end_image_sampled(kk):
+    w = C.VERNIER
+    ds = C.speckle_dataset(w, seed=2, n_scat=100000)
+    su = kk.make_setup(w)
+    got = _frame(kk, su, ds.rf)
+    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    rng = np.random.default_rng(9)
+    xi, zi = rng.integers(0, w.X, 600), rng.integers(0, w.Z, 600)
+    ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    assert _rel(got[:, xi, zi], ref) <= TOL, _rel(got[:, xi, zi], ref)
+
+
+def _das(K, w, rf):
+    import torch
+    g = K.geom(w.L, w.T, w.pitch, w.c, w.fs, w.t0)
+    gr = K.grid(w.X, w.Z, w.x0, w.dx, w.z0, w.dz)
+    sel = K.select_pairs(w.scheme, w.L, w.N, w.theta_max, w.M, w.j_list)
+    luts = K.build_luts(g, gr, sel["tx_theta"], sel["rx_theta"])
+    rx = K.build_das_rx(g, gr)
+    plan = K.das_plan(w.N, g, luts, rx, gr)
+    img = K.das_beamform(K.to_device(rf), g, plan, K.to_device(plan))
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), luts, rx
+
+
+def test_das_tiny_all_pixels(kk):
+    w = C.TINY
+    ds = C.tiny_dataset(1)
+    got, luts, rx = _das(kk, w, ds.rf)
+    rfa = O.analytic_signal(ds.rf, O.next_pow2(w.T))
+    ref = O.das_beamform(rfa, luts["lut1"], luts["lut2"], rx, luts["t0_q"], w.X, w.Z)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+
+
+def test_das_ragged_and_late_start(kk):
+    w = replace(C.TINY, X=70, Z=37, t0=3e-6, T=1000)
+    acq = w.acquisition()
+    ds = make_dataset(acq, seeded_points(12))
+    got, luts, rx = _das(kk, w, ds.rf)
+    rfa = O.analytic_signal(ds.rf, O.next_pow2(w.T))
+    ref = O.das_beamform(rfa, luts["lut1"], luts["lut2"], rx, luts["t0_q"], w.X, w.Z)
+    assert _rel(got, ref) <= TOL, _rel(got, ref)
+
+
+def test_das_vernier_sampled(kk):
+    w = C.VERNIER
+    ds = C.speckle_dataset(w, seed=2, n_scat=20000)
+    got, luts, rx = _das(kk, w, ds.rf)
+    rfa = O.analytic_signal(ds.rf, O.next_pow2(w.T))
+    rng = np.random.default_rng(10)
+    xi, zi = rng.integers(0, w.X, 300), rng.integers(0, w.Z, 300)
+    ref = O.das_beamform(rfa, luts["lut1"], luts["lut2"], rx, luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    assert _rel(got[xi, zi], ref) <= TOL, _rel(got[xi, zi], ref)
+
+
+def test_decompose_errors(kk):
+    import torch
+    w = C.TINY
+    su = kk.make_setup(w)
+    rf = torch.zeros((w.N, w.L, w.T), dtype=torch.int16, device="cuda")
+    sh = kk.to_device(su.luts["shift"])
+    with pytest.raises(kk.KKError) as e:
+        kk.decompose(rf, su.geom, sh, su.M, su.tpad, precision=1)
+    assert e.value.status == kk.KK_E_UNSUPPORTED
+    with pytest.raises(kk.KKError) as e:
+        kk.decompose(rf, su.geom, sh, su.M, 3000)
+    assert e.value.status == kk.KK_E_ARG
+    with pytest.raises(kk.KKError) as e:
+        kk.decompose(rf, su.geom, sh, su.M, su.tpad, ws=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == kk.KK_E_WORKSPACE
