@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the KK beamforming hot path on one MI355X.
+
+Workload (the plain-KK-vs-DAS configuration): 128-element linear array, pitch 0.3 mm,
+5 MHz pulse sampled at 20 MHz, 2048 int16 samples per record, 31 plane-wave transmits in
++-15 deg; two shifted-vernier receive sets (Eq. 6, j = 0 and 15, M = 7: 13 distinct
+receive angles, 434 pair slots, 9.14x compression); speckle phantom of 1e5 scatterers with
+8 point targets and a 2 mm anechoic cyst (seeded, synthetic); 256 lateral x 512 axial
+pixels at lambda/2.
+
+One step = one KK frame from int16 channel data resident in HBM: decomposition (analytic
+FFT, per-bin MFMA contraction, inverse FFT), gather beamforming of both sets and Eq. 9
+compounding.  Selection, delay tables and plans are per-geometry setup, built before timing
+(as the paper's Table II excludes them).  Printed: one JSON line.
+  value            pixel*pair / s of the whole frame (X Z P / step time), in Gpixel*pair/s
+  frames_per_s     KK frames per second;  das_frames_per_s  DAS (Eq. 4) on the same data
+  roofline         gather kernel against the VALU issue bound
+  cpu_baseline     the FP64 oracle, unmodified, on a bounded sample on this host
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "KK beamform Gpixel·pair/s and frames/s vs GPU DAS at rel-L2 ≤1e-5 (FP32)"
+# VALU issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-operations per second,
+# and the algorithmic lane-operations per pixel*pair of the gather (delay add, index
+# extraction, weight conversion, complex interpolate-accumulate with a stored difference).
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+OPS_PER_PIXEL_PAIR = 7
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for cpu_baseline (0: skip)")
+    ap.add_argument("--no-das", action="store_true")
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle check of the timed frame")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (HBM byte-counter calibration)")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the KK path shards frame-parallel across GPUs "
+              "(see DESIGN.md) but no multi-GPU run is provided", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2603_22496_amd import configs as C
+    from paper_2603_22496_amd import kk
+
+    if not os.path.exists(kk.LIB_PATH):
+        from paper_2603_22496_amd.build import build_all
+        build_all()
+    torch.cuda.set_device(0)
+    w = C.VERNIER
+    t0 = time.time()
+    ds = C.speckle_dataset(w, seed=2, n_scat=100_000)
+    su = kk.make_setup(w, with_das=not args.no_das)
+    t_setup = time.time() - t0
+    P = len(su.sel["pairs"])
+    S = su.sel["S"]
+    print("bench: workload vernier N=%d L=%d T=%d M=%d P=%d S=%d grid %dx%d tpad=%d (setup %.1fs)"
+          % (w.N, w.L, w.T, su.M, P, S, w.X, w.Z, su.tpad, t_setup), file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    rf = kk.to_device(ds.rf)
+    shift = kk.to_device(su.luts["shift"])
+    plan_dev = kk.to_device(su.plan)
+    rt = torch.empty((w.N, su.M, w.T), dtype=torch.complex64, device=dev)
+    ws = torch.empty(kk.decompose_workspace_bytes(su.geom, w.N, su.M, su.tpad), dtype=torch.uint8, device=dev)
+    img = torch.empty((S, w.X, w.Z), dtype=torch.complex64, device=dev)
+    inten = torch.empty((w.X, w.Z), dtype=torch.float32, device=dev)
+
+    def frame():
+        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
+        kk.beamform(rt, su.plan, plan_dev, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT)
+
+    def decompose_only():
+        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
+
+    def gather_only():
+        kk.beamform(rt, su.plan, plan_dev, image=img)
+
+    # the timed region: K frames bracketed by synchronisation
+    for _ in range(args.warmup):
+        frame()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.time()
+    e0.record()
+    for _ in range(args.steps):
+        frame()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    ms = e0.elapsed_time(e1) / args.steps
+    print("bench: %d KK frames in %.3fs wall, %.2f us/frame" % (args.steps, wall, ms * 1e3), file=sys.stderr,
+          flush=True)
+
+    ms_dec = timed(decompose_only, args.steps, 5, torch)
+    ms_gather = timed(gather_only, args.steps, 5, torch)
+    res = {}
+    if not args.no_das:
+        das_dev = kk.to_device(su.das_plan)
+        dimg = torch.empty((w.X, w.Z), dtype=torch.complex64, device=dev)
+        dws = torch.empty(kk.das_workspace_bytes(su.geom, w.N), dtype=torch.uint8, device=dev)
+        das_steps = max(10, args.steps // 4)
+        ms_das = timed(lambda: kk.das_beamform(rf, su.geom, su.das_plan, das_dev, image=dimg, ws=dws),
+                       das_steps, 3, torch)
+        res["das_ms"] = ms_das
+        print("bench: DAS %.2f us/frame" % (ms_das * 1e3), file=sys.stderr, flush=True)
+
+    if args.copy_mb > 0:
+        src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # parity of this very frame against the FP64 oracle at sampled pixels (the oracle is
+    # test infrastructure: it checks the timed output, it never produces it)
+    import oracle as O
+    rel = None
+    if not args.no_parity or args.cpu_frames > 0:
+        frame()
+        torch.cuda.synchronize()
+        got = img.cpu().numpy()
+        R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+        rng = np.random.default_rng(0)
+        xi, zi = rng.integers(0, w.X, 500), rng.integers(0, w.Z, 500)
+        ref = O.kk_beamform(R, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                            su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+        rel = float(np.linalg.norm(got[:, xi, zi] - ref) / np.linalg.norm(ref))
+
+    pixpair = w.X * w.Z * P
+    gather_rate = pixpair / (ms_gather * 1e-3)
+    achieved = OPS_PER_PIXEL_PAIR * gather_rate / 1e12
+    peak = VALU_LANE_OPS / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(pixpair / (ms * 1e-3) / 1e9, 2),
+        "unit": "Gpixel·pair/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded speckle + points + cyst phantom, int16 channel data)",
+        "config": {
+            "workload": "vernier: 128 el pitch 0.3 mm, fc 5 MHz, fs 20 MHz, 2048 samples, 31 tx in +-15 deg, "
+                        "Eq.6 sets j=0,15 M=7 (13 rx angles, 434 pairs, 9.14x), 256x512 px, Eq.9 compounding",
+            "N": w.N, "L": w.L, "T": w.T, "M": su.M, "P": P, "S": S, "X": w.X, "Z": w.Z, "tpad": su.tpad,
+        },
+        "frames_per_s": round(1e3 / ms, 1),
+        "stages_us": {"decompose": round(ms_dec * 1e3, 2), "gather": round(ms_gather * 1e3, 2),
+                      "frame": round(ms * 1e3, 2)},
+        "beamform_gpixpair_per_s": round(gather_rate / 1e9, 1),
+        "rel_l2_vs_fp64_oracle": rel,
+        "roofline": {
+            "bound": "alu",
+            "kernel": "gather_kernel (kk_beamform)",
+            "achieved": round(achieved, 3),
+            "peak": round(peak, 3),
+            "unit": "TOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": None,
+            "ops_per_pixel_pair": OPS_PER_PIXEL_PAIR,
+        },
+    }
+    if "das_ms" in res:
+        out["das_frames_per_s"] = round(1e3 / res["das_ms"], 1)
+        out["stages_us"]["das"] = round(res["das_ms"] * 1e3, 2)
+        out["kk_over_das_speedup"] = round(res["das_ms"] / ms, 2)
+
+    if args.cpu_frames > 0:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t = time.time()
+            for _ in range(args.cpu_frames):
+                Rc = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+                O.kk_beamform(Rc, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                              su.luts["lut4"], su.luts["t0_q"], w.X, w.Z)
+            dt = (time.time() - t) / args.cpu_frames
+        out["cpu_baseline"] = {
+            "value": round(pixpair / dt / 1e9, 5),
+            "unit": "Gpixel·pair/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": "%d full vernier KK frames (decompose + beamform, FP64 numpy), %.2f s/frame = %.3f frames/s"
+                      % (args.cpu_frames, dt, 1.0 / dt),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
