@@ -96,16 +96,17 @@ def main():
     ws = torch.empty(kk.decompose_workspace_bytes(su.geom, w.N, su.M, su.tpad), dtype=torch.uint8, device=dev)
     img = torch.empty((S, w.X, w.Z), dtype=torch.complex64, device=dev)
     inten = torch.empty((w.X, w.Z), dtype=torch.float32, device=dev)
+    bws = torch.empty(max(1, kk.beamform_workspace_bytes(su.plan)), dtype=torch.uint8, device=dev)
 
     def frame():
         kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
-        kk.beamform(rt, su.plan, plan_dev, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT)
+        kk.beamform(rt, su.plan, plan_dev, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT, ws=bws)
 
     def decompose_only():
         kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
 
     def gather_only():
-        kk.beamform(rt, su.plan, plan_dev, image=img)
+        kk.beamform(rt, su.plan, plan_dev, image=img, ws=bws)
 
     # the timed region: K frames bracketed by synchronisation
     for _ in range(args.warmup):
@@ -130,7 +131,7 @@ def main():
     if not args.no_das:
         das_dev = kk.to_device(su.das_plan)
         dimg = torch.empty((w.X, w.Z), dtype=torch.complex64, device=dev)
-        dws = torch.empty(kk.das_workspace_bytes(su.geom, w.N), dtype=torch.uint8, device=dev)
+        dws = torch.empty(kk.das_workspace_bytes(su.geom, w.N, su.das_plan), dtype=torch.uint8, device=dev)
         das_steps = max(10, args.steps // 4)
         ms_das = timed(lambda: kk.das_beamform(rf, su.geom, su.das_plan, das_dev, image=dimg, ws=dws),
                        das_steps, 3, torch)

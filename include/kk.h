@@ -203,13 +203,20 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
  *   plan      dev copy of a kk_beamform_plan buffer for the same N, M, T
  *   image     dev out complex float [S][X][Z]
  *   intensity dev out float [X][Z] or NULL: Eq. 8 (mode COHERENT) or Eq. 9 (INCOHERENT)
- *             of the S images, written in the same pass
+ *             of the S images, written in the same call
+ *   ws        dev workspace of kk_beamform_workspace_bytes(plan) bytes (0 and NULL allowed
+ *             when that is 0): partial images when the plan shares a tile's pairs among
+ *             several workgroups (few tiles x sets); they are summed in a fixed order, so
+ *             results are deterministic
  * Errors: KK_E_NULL, KK_E_ARG (N, M, T differ from the plan's), KK_E_WORKSPACE (plan header
- * invalid), KK_E_HIP.  The plan header is read from host memory: pass its host copy too.
+ * invalid, workspace too small), KK_E_HIP.  The plan header is read from host memory: pass
+ * its host copy too.
  * ------------------------------------------------------------------------------------- */
+size_t kk_beamform_workspace_bytes(const void* plan_host, size_t plan_bytes);
 int32_t kk_beamform(const float* rf_theta, int32_t N, int32_t M, int32_t T,
                     const void* plan_host, const void* plan_dev, size_t plan_bytes,
-                    float* image, float* intensity, int32_t mode, void* stream);
+                    float* image, float* intensity, int32_t mode,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* kk_compound (device) - Eq. 8 / Eq. 9 of S per-set images image [S][X][Z] (complex)
  * into intensity [X][Z] (float).  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
@@ -233,9 +240,10 @@ int32_t das_plan(int32_t N, const kk_geom* g, const int32_t* lut1, const int32_t
  *   rf        dev in int16 [N][L][T]
  *   plan      host and dev copies of a das_plan buffer
  *   image     dev out complex float [X][Z]
- *   ws        dev workspace of at least das_workspace_bytes() bytes
+ *   ws        dev workspace of at least das_workspace_bytes(g, N, plan) bytes (analytic
+ *             spectra, analytic channel data, partial images of a split plan)
  * Errors: KK_E_NULL, KK_E_ARG, KK_E_WORKSPACE, KK_E_HIP. */
-size_t das_workspace_bytes(const kk_geom* g, int32_t N);
+size_t das_workspace_bytes(const kk_geom* g, int32_t N, const void* plan_host, size_t plan_bytes);
 int32_t das_beamform(const int16_t* rf, int32_t N, const kk_geom* g,
                      const void* plan_host, const void* plan_dev, size_t plan_bytes,
                      float* image, void* ws, size_t ws_bytes, void* stream);

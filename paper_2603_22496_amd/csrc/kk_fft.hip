@@ -5,9 +5,11 @@
 // Stockham autosort in LDS with radix-16 passes (register-resident 16-point DFTs built from
 // radix-2/4 stages with exact internal constants) and one radix-2/4/8 pass for the remainder,
 // 256 threads per transform.  The first pass reads global memory directly (coalesced), every
-// later pass goes through one LDS round trip; twiddles come from an FP64-evaluated table held
-// in LDS.  Forward transforms take two real int16 records per workgroup as the real and
-// imaginary parts of one complex sequence and unpack them straight into the two masked
+// later pass goes through one LDS round trip (the LDS array carries one pad slot per 16 points
+// so the strided writes of a radix-16 pass spread over the banks).  A twiddle
+// exp(-2 pi i m / n) is the product of two factors, exp(-2 pi i (m >> (log2n-6)) / 64) and
+// exp(-2 pi i (m mod n/64) / n), each evaluated in FP64 by the workgroup into a small LDS table.
+// Forward transforms take two real int16 records per workgroup as the real and imaginary parts of one complex sequence and unpack them straight into the two masked
 // analytic spectra: for 0 < k < n/2, A[k] = Z[k] + conj(Z[n-k]) and
 // B[k] = -i (Z[k] - conj(Z[n-k])) (the x2 of the analytic mask absorbs the 1/2 of the unpack);
 // A[0] = Re Z[0], B[0] = Im Z[0], likewise at k = n/2.
@@ -114,6 +116,25 @@ struct Dft<16, INV> {
     }
 };
 
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// the two twiddle factor tables: fac[0..63] coarse, fac[64..64+n/64) fine
+template <int LOG2N>
+__device__ __forceinline__ void make_factors(float2* fac, int tid) {
+    constexpr int N = 1 << LOG2N;
+    if (tid < 64 + N / 64) {
+        double sn, cs;
+        sincospi(tid < 64 ? 2.0 * tid / 64.0 : 2.0 * (tid - 64) / (double)N, &sn, &cs);
+        fac[tid] = make_float2((float)cs, (float)(-sn));
+    }
+}
+
+template <int LOG2N>
+__device__ __forceinline__ float2 twiddle_of(const float2* fac, int m) {
+    constexpr int N = 1 << LOG2N;
+    return cmul(fac[m >> (LOG2N - 6)], fac[64 + (m & (N / 64 - 1))]);
+}
+
 template <int LOG2N>
 struct FftPlan {
     static constexpr int N = 1 << LOG2N;
@@ -125,14 +146,15 @@ struct FftPlan {
 };
 
 // twiddles of butterfly b in a pass with NS already-combined points: v[r] *= W_{NS R}^{r k}
-template <int N, int R, int NS, bool INV>
-__device__ __forceinline__ void twiddle(float2* v, int b, const float2* tw) {
+template <int LOG2N, int R, int NS, bool INV>
+__device__ __forceinline__ void twiddle(float2* v, int b, const float2* fac) {
+    constexpr int N = 1 << LOG2N;
     if constexpr (NS > 1) {
         const int k = b % NS;
         constexpr int step = N / (NS * R);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-            const float2 w = tw[r * k * step];
+            const float2 w = twiddle_of<LOG2N>(fac, r * k * step);
             v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
         }
     }
@@ -145,8 +167,9 @@ __device__ __forceinline__ int out_index(int b, int r) {
 }
 
 // one Stockham pass LDS -> LDS (in place: all reads, barrier, all writes, barrier)
-template <int N, int R, int NS, bool INV>
-__device__ __forceinline__ void pass_lds(float2* data, const float2* tw, int tid) {
+template <int LOG2N, int R, int NS, bool INV>
+__device__ __forceinline__ void pass_lds(float2* data, const float2* fac, int tid) {
+    constexpr int N = 1 << LOG2N;
     constexpr int NB = N / R;
     constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
     float2 v[PER][R];
@@ -155,8 +178,8 @@ __device__ __forceinline__ void pass_lds(float2* data, const float2* tw, int tid
         const int b = tid + p * kFftThreads;
         if (b < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[p][r] = data[b + r * NB];
-            twiddle<N, R, NS, INV>(v[p], b, tw);
+            for (int r = 0; r < R; ++r) v[p][r] = data[pad(b + r * NB)];
+            twiddle<LOG2N, R, NS, INV>(v[p], b, fac);
             Dft<R, INV>::run(v[p]);
         }
     }
@@ -166,102 +189,153 @@ __device__ __forceinline__ void pass_lds(float2* data, const float2* tw, int tid
         const int b = tid + p * kFftThreads;
         if (b < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) data[out_index<N, R, NS>(b, r)] = v[p][r];
+            for (int r = 0; r < R; ++r) data[pad(out_index<N, R, NS>(b, r))] = v[p][r];
         }
     }
     __syncthreads();
 }
 
 template <int LOG2N, int P, bool INV>
-__device__ __forceinline__ void middle_passes(float2* data, const float2* tw, int tid) {
+__device__ __forceinline__ void middle_passes(float2* data, const float2* fac, int tid) {
     using F = FftPlan<LOG2N>;
     if constexpr (P < F::NPASS - 1) {
-        pass_lds<F::N, F::radix(P), F::ns(P), INV>(data, tw, tid);
-        middle_passes<LOG2N, P + 1, INV>(data, tw, tid);
+        pass_lds<LOG2N, F::radix(P), F::ns(P), INV>(data, fac, tid);
+        middle_passes<LOG2N, P + 1, INV>(data, fac, tid);
     }
 }
 
-template <int N>
-__device__ __forceinline__ void load_table(float2* tw_s, const float2* __restrict__ tw, int tid) {
-    for (int m = tid; m < N; m += kFftThreads) tw_s[m] = tw[m];
-}
+// int16 samples of one record pair as consumed by the first radix-16 pass
+template <int LOG2N>
+struct PairSamples {
+    static constexpr int N = 1 << LOG2N;
+    static constexpr int NB = N / 16;
+    static constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+    short a[PER][16];
+    short b[PER][16];
+};
 
-template <int LOG2N, bool BLOCKED>
-__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
-                                                                  int T, const float2* __restrict__ tw,
-                                                                  float2* __restrict__ out, int L, int ncol,
-                                                                  int kpad) {
-    using F = FftPlan<LOG2N>;
-    constexpr int N = F::N;
-    __shared__ float2 data[N];
-    __shared__ float2 tw_s[N];
-    const int tid = threadIdx.x;
-    const int t0 = 2 * blockIdx.x, t1 = t0 + 1;
+template <int LOG2N>
+__device__ __forceinline__ void load_pair(PairSamples<LOG2N>& ps, const int16_t* __restrict__ rf, int pair,
+                                          int ntraces, int T, int tid) {
+    using PS = PairSamples<LOG2N>;
+    const int t0 = 2 * pair, t1 = t0 + 1;
     const bool has1 = t1 < ntraces;
-    load_table<N>(tw_s, tw, tid);
     const int16_t* a = rf + (size_t)t0 * T;
     const int16_t* b = rf + (size_t)(has1 ? t1 : t0) * T;
-    {  // first pass straight from the int16 records (zero beyond T)
-        constexpr int R = F::radix(0);
-        constexpr int NB = N / R;
-        constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
 #pragma unroll
-        for (int p = 0; p < PER; ++p) {
+    for (int p = 0; p < PS::PER; ++p) {
+        const int bb = tid + p * kFftThreads;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int n = bb + r * PS::NB;
+            const bool ok = bb < PS::NB && n < T;
+            ps.a[p][r] = ok ? a[n] : (short)0;
+            ps.b[p][r] = (ok && has1) ? b[n] : (short)0;
+        }
+    }
+}
+
+// Grid-stride over record pairs; the next pair's samples are loaded into registers while the
+// current pair is transformed.
+template <int LOG2N, bool BLOCKED>
+__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
+                                                                  int T, float2* __restrict__ out, int L, int ncol,
+                                                                  int kpad) {
+    using F = FftPlan<LOG2N>;
+    using PS = PairSamples<LOG2N>;
+    constexpr int N = F::N;
+    static_assert(F::radix(0) == 16, "first pass is radix 16");
+    __shared__ float2 data[N + N / 16];
+    __shared__ float2 fac[64 + N / 64];
+    const int tid = threadIdx.x;
+    const int npairs = (ntraces + 1) / 2;
+    make_factors<LOG2N>(fac, tid);
+    PS cur, nxt;
+    int pair = blockIdx.x;
+    if (pair < npairs) load_pair<LOG2N>(cur, rf, pair, ntraces, T, tid);
+    for (; pair < npairs; pair += gridDim.x) {
+        const int next = pair + gridDim.x;
+        if (next < npairs) load_pair<LOG2N>(nxt, rf, next, ntraces, T, tid);
+        const int t0 = 2 * pair, t1 = t0 + 1;
+        const bool has1 = t1 < ntraces;
+#pragma unroll
+        for (int p = 0; p < PS::PER; ++p) {  // first pass from registers
             const int bb = tid + p * kFftThreads;
-            if (bb < NB) {
-                float2 v[R];
+            if (bb < PS::NB) {
+                float2 v[16];
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int n = bb + r * NB;
-                    v[r] = n < T ? make_float2((float)a[n], has1 ? (float)b[n] : 0.0f) : make_float2(0.f, 0.f);
-                }
-                Dft<R, false>::run(v);
+                for (int r = 0; r < 16; ++r) v[r] = make_float2((float)cur.a[p][r], (float)cur.b[p][r]);
+                Dft<16, false>::run(v);
 #pragma unroll
-                for (int r = 0; r < R; ++r) data[out_index<N, R, 1>(bb, r)] = v[r];
+                for (int r = 0; r < 16; ++r) data[pad(out_index<N, 16, 1>(bb, r))] = v[r];
             }
         }
         __syncthreads();
-    }
-    middle_passes<LOG2N, 1, false>(data, tw_s, tid);
-    pass_lds<N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, tw_s, tid);
-    // unpack the two real spectra with the analytic mask
-    const int i0 = t0 / L, l0 = t0 - i0 * L, i1 = t1 / L, l1 = t1 - i1 * L;
-    for (int k = tid; k <= N / 2; k += kFftThreads) {
-        const float2 zk = data[k];
-        const float2 zm = data[(N - k) & (N - 1)];
-        float2 A, B;
-        if (k == 0 || k == N / 2) {
-            A = make_float2(zk.x, 0.f);
-            B = make_float2(zk.y, 0.f);
-        } else {
-            A = make_float2(zk.x + zm.x, zk.y - zm.y);
-            const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
-            B = make_float2(d.y, -d.x);
+        middle_passes<LOG2N, 1, false>(data, fac, tid);
+        pass_lds<LOG2N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, fac, tid);
+        // unpack the two real spectra with the analytic mask
+        const int i0 = t0 / L, l0 = t0 - i0 * L, i1 = t1 / L, l1 = t1 - i1 * L;
+        for (int k = tid; k <= N / 2; k += kFftThreads) {
+            const float2 zk = data[pad(k)];
+            const float2 zm = data[pad((N - k) & (N - 1))];
+            float2 A, B;
+            if (k == 0 || k == N / 2) {
+                A = make_float2(zk.x, 0.f);
+                B = make_float2(zk.y, 0.f);
+            } else {
+                A = make_float2(zk.x + zm.x, zk.y - zm.y);
+                const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
+                B = make_float2(d.y, -d.x);
+            }
+            if (BLOCKED) {
+                const size_t kb = (size_t)(k >> 3), kk = (size_t)(k & 7);
+                out[(((kb * ncol + i0) * L + l0) << 3) + kk] = A;
+                if (has1) out[(((kb * ncol + i1) * L + l1) << 3) + kk] = B;
+            } else {
+                out[(size_t)t0 * kpad + k] = A;
+                if (has1) out[(size_t)t1 * kpad + k] = B;
+            }
         }
-        if (BLOCKED) {
-            const size_t kb = (size_t)(k >> 3), kk = (size_t)(k & 7);
-            out[(((kb * ncol + i0) * L + l0) << 3) + kk] = A;
-            if (has1) out[(((kb * ncol + i1) * L + l1) << 3) + kk] = B;
-        } else {
-            out[(size_t)t0 * kpad + k] = A;
-            if (has1) out[(size_t)t1 * kpad + k] = B;
-        }
+        __syncthreads();  // the next pair overwrites data
+        cur = nxt;
     }
 }
 
-template <int LOG2N>
+template <int LOG2N, bool NYQ>
 __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* __restrict__ in, int kpad,
-                                                                  const float2* __restrict__ tw,
-                                                                  float2* __restrict__ out, int T) {
+                                                                  float2* __restrict__ out, int T,
+                                                                  NyquistSum nyq) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
     constexpr int K = N / 2 + 1;
-    __shared__ float2 data[N];
-    __shared__ float2 tw_s[N];
+    __shared__ float2 data[N + N / 16];
+    __shared__ float2 fac[64 + N / 64];
     const int tid = threadIdx.x;
     const int t = blockIdx.x;
-    load_table<N>(tw_s, tw, tid);
+    make_factors<LOG2N>(fac, tid);
     const float2* y = in + (size_t)t * kpad;
+    float2 ynyq = make_float2(0.f, 0.f);
+    if constexpr (NYQ) {
+        // Eq. 3 at k = n/2: the advance s gives exp(i pi (s mod 2^23) / 2^22)
+        const int i = t / nyq.M, o = t - (t / nyq.M) * nyq.M;
+        float2 part = make_float2(0.f, 0.f);
+        for (int l = tid; l < nyq.L; l += kFftThreads) {
+            const uint32_t s = (uint32_t)nyq.shift[(size_t)o * nyq.L + l];
+            float sn, cs;
+            sincospif((float)(s & 0x7FFFFFu) * (1.0f / 4194304.0f), &sn, &cs);
+            const float2 x = nyq.X[((((size_t)N / 16) * nyq.ncol + i) * nyq.L + l) * 8];
+            part.x += cs * x.x - sn * x.y;
+            part.y += cs * x.y + sn * x.x;
+        }
+        data[tid] = part;
+        __syncthreads();
+        for (int h = kFftThreads / 2; h > 0; h >>= 1) {
+            if (tid < h) data[tid] = cadd(data[tid], data[tid + h]);
+            __syncthreads();
+        }
+        ynyq = data[0];
+        __syncthreads();
+    }
     {  // first pass from the K non-negative bins (negative bins are zero)
         constexpr int R = F::radix(0);
         constexpr int NB = N / R;
@@ -274,16 +348,16 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int k = bb + r * NB;
-                    v[r] = k < K ? y[k] : make_float2(0.f, 0.f);
+                    v[r] = (NYQ && k == N / 2) ? ynyq : (k < K ? y[k] : make_float2(0.f, 0.f));
                 }
                 Dft<R, true>::run(v);
 #pragma unroll
-                for (int r = 0; r < R; ++r) data[out_index<N, R, 1>(bb, r)] = v[r];
+                for (int r = 0; r < R; ++r) data[pad(out_index<N, R, 1>(bb, r))] = v[r];
             }
         }
         __syncthreads();
     }
-    middle_passes<LOG2N, 1, true>(data, tw_s, tid);
+    middle_passes<LOG2N, 1, true>(data, fac, tid);
     {  // last pass straight to the output record, scaled by 1/N
         constexpr int P = F::NPASS - 1;
         constexpr int R = F::radix(P);
@@ -298,8 +372,8 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
             if (bb < NB) {
                 float2 v[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = data[bb + r * NB];
-                twiddle<N, R, NS, true>(v, bb, tw_s);
+                for (int r = 0; r < R; ++r) v[r] = data[pad(bb + r * NB)];
+                twiddle<LOG2N, R, NS, true>(v, bb, fac);
                 Dft<R, true>::run(v);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -311,64 +385,56 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
     }
 }
 
-__global__ void twiddle_kernel(float2* tw, int log2n) {
-    const int n = 1 << log2n;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    double s, c;
-    sincospi(2.0 * (double)m / (double)n, &s, &c);
-    tw[m] = make_float2((float)c, (float)(-s));
-}
-
 template <int LOG2N>
-hipError_t fwd(const int16_t* rf, int ntraces, int T, const float2* tw, float2* out, bool blocked, int L, int ncol,
-               int kpad, hipStream_t st) {
-    const int blocks = (ntraces + 1) / 2;
+hipError_t fwd(const int16_t* rf, int ntraces, int T, float2* out, bool blocked, int L, int ncol, int kpad,
+               hipStream_t st) {
+    // about three record pairs per workgroup, four workgroups per CU
+    const int npairs = (ntraces + 1) / 2;
+    const int blocks = npairs < 1024 ? npairs : (npairs + 2) / 3 < 1024 ? 1024 : (npairs + 2) / 3;
     if (blocked)
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces, T,
-                           tw, out, L, ncol, kpad);
+                           out, L, ncol, kpad);
     else
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, false>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces,
-                           T, tw, out, L, ncol, kpad);
+                           T, out, L, ncol, kpad);
     return hipGetLastError();
 }
 
 template <int LOG2N>
-hipError_t inv(const float2* in, int ntraces, int kpad, const float2* tw, float2* out, int T, hipStream_t st) {
-    hipLaunchKernelGGL((fft_inverse_kernel<LOG2N>), dim3(ntraces), dim3(kFftThreads), 0, st, in, kpad, tw, out, T);
+hipError_t inv(const float2* in, int ntraces, int kpad, float2* out, int T, hipStream_t st, const NyquistSum* nyq) {
+    if (nyq)
+        hipLaunchKernelGGL((fft_inverse_kernel<LOG2N, true>), dim3(ntraces), dim3(kFftThreads), 0, st, in, kpad, out,
+                           T, *nyq);
+    else
+        hipLaunchKernelGGL((fft_inverse_kernel<LOG2N, false>), dim3(ntraces), dim3(kFftThreads), 0, st, in, kpad,
+                           out, T, NyquistSum{nullptr, nullptr, 1, 1, 32});
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_twiddles(float2* tw, int log2n, hipStream_t st) {
-    const int n = 1 << log2n;
-    hipLaunchKernelGGL(twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, st, tw, log2n);
-    return hipGetLastError();
-}
-
-hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, const float2* tw, float2* out,
-                              bool blocked, int L, int ncol, int kpad, hipStream_t st) {
+hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
+                              int ncol, int kpad, hipStream_t st) {
     switch (log2n) {
-        case 8: return fwd<8>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
-        case 9: return fwd<9>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
-        case 10: return fwd<10>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
-        case 11: return fwd<11>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
-        case 12: return fwd<12>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
-        case 13: return fwd<13>(rf, ntraces, T, tw, out, blocked, L, ncol, kpad, st);
+        case 8: return fwd<8>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
+        case 9: return fwd<9>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
+        case 10: return fwd<10>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
+        case 11: return fwd<11>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
+        case 12: return fwd<12>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
+        case 13: return fwd<13>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fft_inverse(const float2* in, int ntraces, int kpad, int log2n, const float2* tw, float2* out,
-                              int T, hipStream_t st) {
+hipError_t launch_fft_inverse(const float2* in, int ntraces, int kpad, int log2n, float2* out, int T,
+                              hipStream_t st, const NyquistSum* nyq) {
     switch (log2n) {
-        case 8: return inv<8>(in, ntraces, kpad, tw, out, T, st);
-        case 9: return inv<9>(in, ntraces, kpad, tw, out, T, st);
-        case 10: return inv<10>(in, ntraces, kpad, tw, out, T, st);
-        case 11: return inv<11>(in, ntraces, kpad, tw, out, T, st);
-        case 12: return inv<12>(in, ntraces, kpad, tw, out, T, st);
-        case 13: return inv<13>(in, ntraces, kpad, tw, out, T, st);
+        case 8: return inv<8>(in, ntraces, kpad, out, T, st, nyq);
+        case 9: return inv<9>(in, ntraces, kpad, out, T, st, nyq);
+        case 10: return inv<10>(in, ntraces, kpad, out, T, st, nyq);
+        case 11: return inv<11>(in, ntraces, kpad, out, T, st, nyq);
+        case 12: return inv<12>(in, ntraces, kpad, out, T, st, nyq);
+        case 13: return inv<13>(in, ntraces, kpad, out, T, st, nyq);
         default: return hipErrorInvalidValue;
     }
 }

@@ -325,6 +325,14 @@ int32_t pick_cap(int64_t max_w) {
 
 int64_t floor_div65536(int64_t q) { return q >> 16; }  // arithmetic shift = floor for int64
 
+// Pair shares per (set, tile): enough workgroups to cover the CUs while every share keeps at
+// least two batches of pairs.
+int32_t choose_split(int64_t units, int64_t min_set_pairs, int32_t pb) {
+    int32_t k = 1;
+    while (k < kk::kMaxSplit && units * k < kk::kTargetWorkgroups && min_set_pairs >= (int64_t)(k + 1) * 2 * pb) ++k;
+    return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -447,6 +455,9 @@ int32_t kk_beamform_plan(const int32_t* pairs, int32_t P, int32_t S, int32_t N, 
     off += (int64_t)lo.size();
     w[PW_OFF_C] = 0;
     w[PW_TOTAL] = (int32_t)off;
+    int64_t min_set = P;
+    for (int32_t s = 0; s < S; ++s) min_set = std::min<int64_t>(min_set, set_start[s + 1] - set_start[s]);
+    w[PW_SPLIT] = choose_split(ntiles * S, min_set, pairs_per_batch(cap));
     return off == words ? KK_OK : KK_E_ARG;
 }
 
@@ -555,6 +566,7 @@ int32_t das_plan(int32_t N, const kk_geom* g, const int32_t* lut1, const int32_t
     std::memcpy(w + off, C.data(), C.size() * 4);
     off += (int64_t)C.size();
     w[PW_TOTAL] = (int32_t)off;
+    w[PW_SPLIT] = choose_split(ntiles, P, pairs_per_batch(cap));
     return off == words ? KK_OK : KK_E_ARG;
 }
 

@@ -14,6 +14,11 @@ constexpr int32_t kPlanKindDAS = 1;
 constexpr int32_t kTileX = 64;
 constexpr int32_t kTileZ = 16;
 
+// Largest pair split: a (set, tile) is shared by up to this many workgroups when there are
+// fewer (set, tile) units than CUs, their partial images summed in a fixed order afterwards.
+constexpr int32_t kMaxSplit = 8;
+constexpr int32_t kTargetWorkgroups = 256;  // one per CU of an MI355X
+
 // Window slot capacities (record samples per pair and tile) for which kernels exist.
 constexpr int32_t kCaps[] = {64, 128, 192, 256, 320, 384, 448, 512};
 constexpr int32_t kNumCaps = 8;
@@ -52,6 +57,7 @@ enum PlanWord : int32_t {
     PW_OFF_C,      // DAS: int32[L][ZPAD][XPAD] receive delay, x fastest; KK: 0
     PW_OFF_TX,     // DAS: int32[P] transmit index of pair p (A/B row); KK: pair index p
     PW_TOTAL,      // plan length in words
+    PW_SPLIT,      // pair shares per (set, tile): workgroups = tiles * S * SPLIT
     PW_HEADER_WORDS = 32
 };
 

@@ -28,8 +28,8 @@ COMPOUND_COHERENT, COMPOUND_INCOHERENT = 0, 1
 
 EXPORTS = [
     "kk_select_pairs", "kk_build_luts", "kk_build_das_rx", "kk_beamform_plan",
-    "kk_decompose_workspace_bytes", "kk_decompose", "kk_beamform", "kk_compound",
-    "das_plan", "das_workspace_bytes", "das_beamform", "kk_status_string",
+    "kk_decompose_workspace_bytes", "kk_decompose", "kk_beamform_workspace_bytes", "kk_beamform",
+    "kk_compound", "das_plan", "das_workspace_bytes", "das_beamform", "kk_status_string",
 ]
 
 
@@ -74,7 +74,7 @@ def lib():
             "kk_beamform_plan": [_i32p, _i32, _i32, _i32, _i32, _i32, _i32p, _i32p, _i32p, _i32p, _i32,
                                  ctypes.POINTER(Grid), _vp, _sz, _szp],
             "kk_decompose": [_vp, _i32, ctypes.POINTER(Geom), _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp],
-            "kk_beamform": [_vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp, _vp, _i32, _vp],
+            "kk_beamform": [_vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp, _vp, _i32, _vp, _sz, _vp],
             "kk_compound": [_vp, _i32, _i32, _i32, _i32, _vp, _vp],
             "das_plan": [_i32, ctypes.POINTER(Geom), _i32p, _i32p, _i32p, _i32, ctypes.POINTER(Grid), _vp, _sz,
                          _szp],
@@ -87,8 +87,10 @@ def lib():
                 fn.restype = _i32
         L.kk_decompose_workspace_bytes.argtypes = [ctypes.POINTER(Geom), _i32, _i32, _i32, _i32]
         L.kk_decompose_workspace_bytes.restype = _sz
-        L.das_workspace_bytes.argtypes = [ctypes.POINTER(Geom), _i32]
+        L.das_workspace_bytes.argtypes = [ctypes.POINTER(Geom), _i32, _vp, _sz]
         L.das_workspace_bytes.restype = _sz
+        L.kk_beamform_workspace_bytes.argtypes = [_vp, _sz]
+        L.kk_beamform_workspace_bytes.restype = _sz
         L.kk_status_string.argtypes = [_i32]
         L.kk_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -232,16 +234,24 @@ def decompose(rf, g: Geom, shift_q, M: int, tpad: int, out=None, ws=None, precis
     return out
 
 
+def beamform_workspace_bytes(plan_host: np.ndarray) -> int:
+    return int(lib().kk_beamform_workspace_bytes(plan_host.ctypes.data_as(_vp), plan_host.nbytes))
+
+
 def beamform(rf_theta, plan_host: np.ndarray, plan_dev, image=None, intensity=None,
-             mode: int = COMPOUND_COHERENT, stream=None):
+             mode: int = COMPOUND_COHERENT, ws=None, stream=None):
     """rf_theta complex64 [N][M][T] -> per-set images complex64 [S][X][Z] (and intensity)."""
     N, M, T = rf_theta.shape
     S, X, Z = int(plan_host[6]), int(plan_host[7]), int(plan_host[8])
     if image is None:
         image = torch.empty((S, X, Z), dtype=torch.complex64, device=rf_theta.device)
+    need = beamform_workspace_bytes(plan_host)
+    if ws is None and need > 0:
+        ws = torch.empty(need, dtype=torch.uint8, device=rf_theta.device)
     st = lib().kk_beamform(_dev(rf_theta), N, M, T, plan_host.ctypes.data_as(_vp), _dev(plan_dev),
                            plan_host.nbytes, _dev(image), _dev(intensity) if intensity is not None else None,
-                           mode, _stream(stream))
+                           mode, _dev(ws) if ws is not None else None,
+                           ws.numel() * ws.element_size() if ws is not None else 0, _stream(stream))
     _check("kk_beamform", st)
     return image
 
@@ -254,8 +264,8 @@ def compound(image, mode: int = COMPOUND_COHERENT, out=None, stream=None):
     return out
 
 
-def das_workspace_bytes(g: Geom, N: int) -> int:
-    return int(lib().das_workspace_bytes(ctypes.byref(g), N))
+def das_workspace_bytes(g: Geom, N: int, plan_host: np.ndarray) -> int:
+    return int(lib().das_workspace_bytes(ctypes.byref(g), N, plan_host.ctypes.data_as(_vp), plan_host.nbytes))
 
 
 def das_beamform(rf, g: Geom, plan_host: np.ndarray, plan_dev, image=None, ws=None, stream=None):
@@ -263,7 +273,7 @@ def das_beamform(rf, g: Geom, plan_host: np.ndarray, plan_dev, image=None, ws=No
     X, Z = int(plan_host[7]), int(plan_host[8])
     if image is None:
         image = torch.empty((X, Z), dtype=torch.complex64, device=rf.device)
-    nbytes = das_workspace_bytes(g, N)
+    nbytes = das_workspace_bytes(g, N, plan_host)
     if ws is None:
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=rf.device)
     st = lib().das_beamform(_dev(rf), N, ctypes.byref(g), plan_host.ctypes.data_as(_vp), _dev(plan_dev),

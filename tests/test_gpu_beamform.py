@@ -40,11 +40,15 @@ def _case(K, w, ds, scheme=None, M=None, jl=None, seed=0):
     return su, R32
 
 
-def _run(K, su, R32):
+SPLIT_WORD = 24    # plan header word: pair shares per (set, tile)
+
+
+def _run(K, su, R32, plan=None):
     import torch
+    plan = su.plan if plan is None else plan
     rt = K.to_device(R32)
-    pd = K.to_device(su.plan)
-    img = K.beamform(rt, su.plan, pd)
+    pd = K.to_device(plan)
+    img = K.beamform(rt, plan, pd)
     torch.cuda.synchronize()
     return img.cpu().numpy()
 
@@ -93,11 +97,31 @@ def test_random_record_values(kk):
     assert _rel(got, ref) <= TOL_BF
 
 
+def test_pair_split_factors(kk):
+    # every share count gives the oracle's image: shares of unequal length, empty shares
+    # (more shares than batches), and the partial images summed in the fixed order
+    w = replace(C.TINY, X=70, Z=37)
+    ds = C.tiny_dataset(6)
+    su, R32 = _case(kk, w, ds, C.SCHEME_SHIFTED, 5, (0, 1))
+    ref = _oracle_img(su, R32)
+    base = _run(kk, su, R32)
+    for k in (1, 2, 3, 5, 8):
+        plan = su.plan.copy()
+        plan[SPLIT_WORD] = k
+        assert kk.beamform_workspace_bytes(plan) == (0 if k == 1 else k * su.sel["S"] * w.X * w.Z * 8)
+        got = _run(kk, su, R32, plan)
+        assert _rel(got, ref) <= TOL_BF, (k, _rel(got, ref))
+        if k == 1:
+            assert np.array_equal(got.view(np.uint32), base.view(np.uint32))
+
+
 @pytest.mark.parametrize("wname", ["vernier", "full"])
 def test_full_size_sampled_pixels(kk, wname):
     w = C.WORKLOADS[wname]
     ds = C.speckle_dataset(C.VERNIER, seed=2, n_scat=20000)
     su, R32 = _case(kk, w, ds)
+    if wname == "full":   # one set: fewer tiles than CUs, the plan splits the pairs
+        assert su.plan[SPLIT_WORD] > 1
     got = _run(kk, su, R32)
     rng = np.random.default_rng(7)
     xi = rng.integers(0, w.X, 400)
@@ -130,9 +154,15 @@ def test_deterministic(kk):
     a = _run(kk, su, R32)
     b = _run(kk, su, R32)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    plan = su.plan.copy()
+    plan[SPLIT_WORD] = 4
+    a = _run(kk, su, R32, plan)
+    b = _run(kk, su, R32, plan)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
 
 
 def test_argument_errors(kk):
+    import torch
     ds = C.tiny_dataset(0)
     su, R32 = _case(kk, C.TINY, ds)
     rt, pd = kk.to_device(R32), kk.to_device(su.plan)
@@ -143,4 +173,14 @@ def test_argument_errors(kk):
     bad[0] = 0
     with pytest.raises(kk.KKError) as e:
         kk.beamform(rt, bad, pd)
+    assert e.value.status == kk.KK_E_WORKSPACE
+    split = su.plan.copy()
+    split[SPLIT_WORD] = 2
+    small = torch.empty(kk.beamform_workspace_bytes(split) - 8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(kk.KKError) as e:          # share buffer too small
+        kk.beamform(rt, split, kk.to_device(split), ws=small)
+    assert e.value.status == kk.KK_E_WORKSPACE
+    split[SPLIT_WORD] = 9                         # beyond the largest split
+    with pytest.raises(kk.KKError) as e:
+        kk.beamform(rt, split, pd)
     assert e.value.status == kk.KK_E_WORKSPACE

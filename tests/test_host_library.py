@@ -26,7 +26,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # word indices of the plan header (paper_2603_22496_amd/csrc/kk_plan.h)
 PW = dict(MAGIC=0, KIND=1, N=2, M=3, T=4, P=5, S=6, X=7, Z=8, NXT=9, NZT=10, XPAD=11, ZPAD=12, CAP=13,
           MAXW=14, PB=15, OFF_SET=16, OFF_REC=17, OFF_A=18, OFF_B=19, OFF_LO=20, OFF_C=21, OFF_TX=22,
-          TOTAL=23)
+          TOTAL=23, SPLIT=24)
+
+
+def _check_split(h, units, min_set_pairs):
+    # pair shares per (set, tile): up to 8, grown while the launch has fewer than 256 workgroups
+    # and every share keeps at least two batches of pairs
+    k, pb = h["SPLIT"], h["PB"]
+    assert 1 <= k <= 8
+    assert k == 1 or (units * (k - 1) < 256 and min_set_pairs >= k * 2 * pb)
+    assert k == 8 or units * k >= 256 or min_set_pairs < (k + 1) * 2 * pb
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -213,9 +222,13 @@ def _check_kk_plan(plan, sel, ora, w):
         rel = idx - lo[t][:, None, None]
         assert rel.min() >= 0 and rel.max() <= cap - 1
         assert rel.min(axis=(1, 2)).max() == 0                     # lo is exact
+    _check_split(h, nxt * nzt * S, int(np.diff(sets).min()))
+    need = kk.beamform_workspace_bytes(plan)
+    assert need == (0 if h["SPLIT"] == 1 else h["SPLIT"] * S * w.X * w.Z * 8)
 
 
-@pytest.mark.parametrize("wname", ["tiny", "vernier"])
+# "full": one set over a 128-angle bank, fewer (set, tile) units than CUs, so pairs are split
+@pytest.mark.parametrize("wname", ["tiny", "vernier", "full"])
 def test_kk_plan_windows_cover_every_delay(wname):
     w = C.WORKLOADS[wname]
     sel, ora, lib, g, gr = _both_luts(w)
@@ -285,3 +298,7 @@ def test_das_plan_windows_cover_every_delay():
                  + Cc[l, zt * 16:(zt + 1) * 16, xt * 64:(xt + 1) * 64])
             rel = (q >> 16) - lo[t, p]
             assert rel.min() == 0 and rel.max() <= h["CAP"] - 1
+    _check_split(h, nxt * nzt, P)
+    need = kk.das_workspace_bytes(g, N, plan)
+    part = 0 if h["SPLIT"] == 1 else h["SPLIT"] * w.X * w.Z * 8
+    assert need >= part + N * L * w.T * 8 and need > 0
