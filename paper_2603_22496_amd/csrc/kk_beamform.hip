@@ -2,24 +2,26 @@
 // Eq. 8 / Eq. 9 compounding epilogue.
 //
 // One workgroup = one 64 (lateral) x 16 (axial) pixel tile of one set (and one share of its
-// pairs when the plan splits them), 16 wave64s: 4 pair groups x 4 axial quarters.  Lane k of
-// a wave owns lateral pixel k of the tile and four consecutive axial pixels, so neighbouring
-// lanes read neighbouring record samples (adjacent lateral pixels differ by at most ~1 sample
-// of delay at lambda/2 pitch) and the LDS gather is broadcast- or stride-1.
+// pairs when the plan splits them), 16 wave64s.  Each wave takes a contiguous run of the
+// share's pairs and forms the whole tile for them: lane k owns lateral pixel k and all 16
+// rows, so neighbouring lanes read neighbouring record samples (adjacent lateral pixels
+// differ by at most ~1 sample of delay at lambda/2 pitch) and the LDS gather is broadcast- or
+// stride-1.  The 16 partial tiles are summed in LDS at the end, in wave order.
 //
-// Pairs are processed in batches.  For every pair of a batch the workgroup stages into LDS the
-// record window the tile touches, as 16-byte entries (R[n], (R[n+1]-R[n]) 2^-16) for
-// n = lo .. lo+cap-1 (zero outside [0, T); lo is exact per pair and tile, from the plan), and
-// the pair's 64 lateral delays A[p][x].  The axial delays B[p][z] of a wave's four rows are the
-// same for all its lanes: they are fetched with scalar loads once per batch, right after the
-// barrier, and the window start and LDS slot are folded into them on the scalar unit, so the
-// integer part of A + B'' is directly the LDS entry of the sample.  Each pixel-pair then costs
-// one integer add, one SDWA shift (entry -> byte address), one SDWA convert of the 16-bit
-// fraction, one ds_read_b128 and two adds plus two FMAs:
+// A wave owns one LDS window slot.  For its current pair the slot holds the record window
+// the tile touches, as 16-byte entries (R[n], (R[n+1]-R[n]) 2^-16) for n = lo .. lo+cap-1
+// (zero outside [0, T); lo is exact per pair and tile, from the plan).  While the wave gathers
+// pair p it has the window and delays of pair p+1 in flight from global memory into
+// registers; it stores that window over its slot after the gather (a wave's LDS operations
+// execute in order), so the pair loop has no workgroup barrier at all.  The delays live in
+// registers: the lateral delay A[p][x] at the lane's pixel, and the 16 axial delays B[p][z]
+// of the tile's rows, with the window start and slot folded in, one per lane of a DPP row.
+// The integer part of A + B'' is then directly the LDS entry of the sample, and each
+// pixel-pair costs one DPP broadcast add, one SDWA shift (entry -> byte address), one SDWA
+// convert of the 16-bit fraction, one ds_read_b128 and two adds plus two FMAs:
 //   acc += R[idx] + frac * (R[idx+1]-R[idx]) 2^-16 = (1 - w) R[idx] + w R[idx+1], w = frac/65536.
-// The four pair groups are reduced through LDS at the end.  Batches are double-buffered: the
-// global loads of batch b+1 are issued before batch b is gathered.  DAS adds a third delay term
-// (receive table, per pixel and element) read once per batch into registers.
+// DAS adds a third delay term, the receive delay of the pair's element at each pixel, held in
+// 16 registers and refetched when the wave's pair run moves to the next element.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -32,8 +34,8 @@ namespace {
 
 constexpr int kWaves = 16;
 constexpr int kThreads = kWaves * 64;
-constexpr int kGroups = 4;       // pair groups per workgroup
-constexpr int kRows = 4;         // axial pixels per lane
+constexpr int kRows = kTileZ;    // axial pixels per lane: the tile's rows
+constexpr int kMetaLanes = 64;   // pairs whose slot metadata a wave holds at once
 
 struct __attribute__((aligned(8))) F4a8 {
     float x, y, z, w;
@@ -48,6 +50,12 @@ __device__ __forceinline__ uint32_t entry_byte_offset(uint32_t q) {
     return a;
 }
 
+// x + bv[lane V of this lane's row of 16 lanes]: one v_add_u32_dpp row_newbcast.
+template <int V>
+__device__ __forceinline__ uint32_t add_row_broadcast(uint32_t bv, uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)bv, 0x150 + V, 0xf, 0xf, true) + x;
+}
+
 // Maps the launch index onto a work unit so that each of the 8 XCDs (workgroups are dealt to
 // XCDs round-robin) receives a contiguous run of units: tiles are numbered depth-major, so an
 // XCD's L2 holds only its depth band of every record.
@@ -57,123 +65,189 @@ __device__ __forceinline__ int xcd_remap(int id, int total) {
     return xcd * base + (xcd < rem ? xcd : rem) + k;
 }
 
-template <int CAP, int PB, bool DAS>
+template <int CAP>
 struct Lds {
-    static constexpr int kWinBytes = 2 * PB * CAP * 16;
-    static constexpr int kABytes = 2 * PB * 64 * 4;
-    static constexpr int kCBytes = DAS ? 2 * 2 * 1024 * 4 : 0;  // DAS: two elements per buffer
-    static constexpr int kBytes = kWinBytes + kABytes + kCBytes;
+    static constexpr int kWinBytes = kWaves * CAP * 16;
+    static constexpr int kRedBytes = kWaves * kRows * 64 * 8;  // partial tiles of all waves
+    static constexpr int kBytes = kWinBytes > kRedBytes ? kWinBytes : kRedBytes;
     static_assert(kBytes <= 160 * 1024, "LDS budget");
-    static_assert(kWinBytes / 16 < 65536, "entry index must fit 16 bits");
-    static_assert(3 * 256 * kRows * 8 <= kBytes, "reduction scratch fits the buffers");
+    static_assert(kWaves * CAP < 65536, "entry index must fit 16 bits");
 };
 
-// Global loads of one batch, held in registers while the previous batch is gathered.
+// Window entries of one pair, held in registers from their global load to their LDS store.
 template <int CAP>
-struct Prefetch {
-    F4a8 v[2][CAP / 64];  // (R[n], R[n+1]) per row of 64 entries, up to two slots per wave
-    int32_t a[2];
-    int32_t c[2];         // DAS: receive delay of pixel (wave row, lane) for two elements
+struct Window {
+    F4a8 v[CAP / 64];
+};
+
+// Delays of one pair for one wave.
+struct PairDelays {
+    uint32_t a;   // lateral delay at pixel `lane`
+    uint32_t b;   // axial delay of row (lane & 15); window start and slot folded in once loaded
+    int32_t lo;   // window start (uniform)
 };
 
 struct PlanView {
-    int T, P, N, xpad, zpad, xt, zt, tile, off_rec, off_a, off_b, off_lo, off_c, off_tx;
+    int T, P, N, xpad, zpad, xt, zt, tile, off_rec, off_a, off_b, off_lo, off_c;
 };
 
-template <int CAP, int PB, bool DAS>
-__device__ __forceinline__ void load_batch(Prefetch<CAP>& pf, const float2* __restrict__ rec,
-                                           const int32_t* __restrict__ plan, const PlanView& pv, int q0, int nb,
-                                           int wave, int lane) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int j = wave + u * kWaves;
-        if (j < nb) {
-            const int q = q0 + j;
-            const int lo = plan[pv.off_lo + pv.tile * pv.P + q];
-            const float2* rp = rec + (size_t)plan[pv.off_rec + q] * pv.T;
-#pragma unroll
-            for (int r = 0; r < CAP / 64; ++r) {
-                const int n = lo + r * 64 + lane;
-                F4a8 v;
-                if ((unsigned)n < (unsigned)(pv.T - 1)) {
-                    v = *reinterpret_cast<const F4a8*>(rp + n);
-                } else {
-                    float2 a = ((unsigned)n < (unsigned)pv.T) ? rp[n] : make_float2(0.f, 0.f);
-                    float2 b = ((unsigned)(n + 1) < (unsigned)pv.T) ? rp[n + 1] : make_float2(0.f, 0.f);
-                    v.x = a.x;
-                    v.y = a.y;
-                    v.z = b.x;
-                    v.w = b.y;
-                }
-                pf.v[u][r] = v;
-            }
-            const int row = DAS ? plan[pv.off_tx + q] : q;  // DAS: transmit delays are per transmit
-            pf.a[u] = plan[pv.off_a + row * pv.xpad + pv.xt * 64 + lane];
-        }
-    }
-    if constexpr (DAS) {
-        // receive delays of the (at most two) elements of this batch, pixel (row = wave, lane)
-        const int l0 = q0 / pv.N;
-        const int nl = (q0 + nb - 1) / pv.N - l0 + 1;
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (u < nl)
-                pf.c[u] = plan[pv.off_c + ((size_t)(l0 + u) * pv.zpad + pv.zt * 16 + wave) * pv.xpad + pv.xt * 64 +
-                               lane];
-    }
+template <bool DAS>
+__device__ __forceinline__ int delay_row(int q, int N) {
+    return DAS ? q % N : q;  // DAS pairs run element-major: p = l N + i, rows are transmits
 }
 
-template <int CAP, int PB, bool DAS>
-__device__ __forceinline__ void store_batch(const Prefetch<CAP>& pf, unsigned char* lds, int buf, int nb,
-                                            const PlanView& pv, int q0, int wave, int lane) {
-    using L = Lds<CAP, PB, DAS>;
-    float4* win = reinterpret_cast<float4*>(lds);
-    int32_t* aslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes);
+// Window start and record of pairs q0 .. q0+63 (lane j holding pair q0 + j, clamped to qend-1).
+struct SlotMeta {
+    int32_t lo;
+    int32_t rec;
+};
+
+__device__ __forceinline__ void load_meta(SlotMeta& m, const int32_t* __restrict__ plan, const PlanView& pv, int q0,
+                                          int qend, int lane) {
+    const int q = min(q0 + lane, qend - 1);
+    m.lo = plan[pv.off_lo + pv.tile * pv.P + q];
+    m.rec = plan[pv.off_rec + q];
+}
+
+// Issues the global loads of pair q (window entries and delays); j = q - (first pair of the
+// metadata run) selects the pair's metadata lane.
+template <int CAP, bool DAS>
+__device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const SlotMeta& m, int j,
+                                          const float2* __restrict__ rec, const int32_t* __restrict__ plan,
+                                          const PlanView& pv, int q, int lane) {
+    const unsigned ulane = (unsigned)lane;
+    const int lo = __builtin_amdgcn_readlane(m.lo, j);
+    const int ri = __builtin_amdgcn_readlane(m.rec, j);
+    const float2* rp = rec + (size_t)ri * pv.T;
+    if (lo >= 0 && lo + CAP <= pv.T - 1) {
+        // the whole window and its right neighbours lie inside the record
+        const float2* src = rp + lo;
+#pragma unroll
+        for (int r = 0; r < CAP / 64; ++r) wn.v[r] = *reinterpret_cast<const F4a8*>(src + r * 64 + ulane);
+    } else {
+#pragma unroll
+        for (int r = 0; r < CAP / 64; ++r) {
+            const int n = lo + r * 64 + lane;
+            const float2 a = ((unsigned)n < (unsigned)pv.T) ? rp[n] : make_float2(0.f, 0.f);
+            const float2 b = ((unsigned)(n + 1) < (unsigned)pv.T) ? rp[n + 1] : make_float2(0.f, 0.f);
+            wn.v[r] = F4a8{a.x, a.y, b.x, b.y};
+        }
+    }
+    const int row = delay_row<DAS>(q, pv.N);
+    d.a = (uint32_t)(plan + pv.off_a + pv.xt * 64 + (unsigned)(row * pv.xpad))[ulane];
+    d.b = (uint32_t)(plan + pv.off_b + pv.zt * kRows + (unsigned)(row * pv.zpad))[ulane & 15];
+    d.lo = lo;
+}
+
+// Folds the window start and the wave's slot into the axial delays once their loads have
+// landed (called after the gather of the previous pair, so the loads stay in flight during it).
+template <int CAP>
+__device__ __forceinline__ void fold_delays(PairDelays& d, int wave) {
+    d.b += (uint32_t)(wave * CAP - d.lo) << 16;
+}
+
+template <int CAP>
+__device__ __forceinline__ void store_window(const Window<CAP>& wn, float4* slot, int lane) {
     const float scale = 1.0f / 65536.0f;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int j = wave + u * kWaves;
-        if (j < nb) {
-            const int slot = buf * PB + j;
-#pragma unroll
-            for (int r = 0; r < CAP / 64; ++r) {
-                const F4a8 v = pf.v[u][r];
-                win[slot * CAP + r * 64 + lane] =
-                    make_float4(v.x, v.y, (v.z - v.x) * scale, (v.w - v.y) * scale);
-            }
-            aslot[slot * 64 + lane] = pf.a[u];
-        }
-    }
-    if constexpr (DAS) {
-        int32_t* cslot = reinterpret_cast<int32_t*>(lds + L::kWinBytes + L::kABytes);
-        const int l0 = q0 / pv.N;
-        const int nl = (q0 + nb - 1) / pv.N - l0 + 1;
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (u < nl) cslot[((buf * 2 + u) * 16 + wave) * 64 + lane] = pf.c[u];
+    for (int r = 0; r < CAP / 64; ++r) {
+        const F4a8 v = wn.v[r];
+        slot[r * 64 + lane] = make_float4(v.x, v.y, (v.z - v.x) * scale, (v.w - v.y) * scale);
     }
 }
 
-// pairs of the next batch: at most PB, and for DAS at most two elements (l) per batch
-template <int PB, bool DAS>
-__device__ __forceinline__ int batch_size(int q, int p_end, int N) {
-    int nb = min(PB, p_end - q);
-    if (DAS) nb = min(nb, (q / N + 2) * N - q);
-    return nb;
+// Rows in flight per pipeline step: four for KK; two for DAS, whose 16 receive delays take
+// the registers of the other two.
+template <bool DAS>
+struct Step {
+    static constexpr int kRowsPerStep = DAS ? 2 : 4;
+};
+
+// One step's samples in flight: their LDS entries and lerp weights.
+template <bool DAS>
+struct RowSamples {
+    float4 e[Step<DAS>::kRowsPerStep];
+    float w[Step<DAS>::kRowsPerStep];
+};
+
+template <int K, bool DAS>
+__device__ __forceinline__ uint32_t row_delay(const PairDelays& d, const uint32_t* c) {
+    return add_row_broadcast<K>(d.b, DAS ? d.a + c[K] : d.a);
 }
 
-template <int CAP, int PB, bool DAS>
+template <int K0, bool DAS>
+__device__ __forceinline__ void issue_rows(RowSamples<DAS>& rs, const PairDelays& d, const uint32_t* c,
+                                           const unsigned char* win) {
+    constexpr int kS = Step<DAS>::kRowsPerStep;
+    uint32_t q[kS];
+    q[0] = row_delay<K0 + 0, DAS>(d, c);
+    q[1] = row_delay<K0 + 1, DAS>(d, c);
+    if constexpr (kS == 4) {
+        q[2] = row_delay<K0 + 2, DAS>(d, c);
+        q[3] = row_delay<K0 + 3, DAS>(d, c);
+    }
+#pragma unroll
+    for (int k = 0; k < kS; ++k) {
+        rs.w[k] = (float)(q[k] & 0xFFFFu);
+        rs.e[k] = *reinterpret_cast<const float4*>(win + entry_byte_offset(q[k]));
+    }
+}
+
+template <int K0, bool DAS>
+__device__ __forceinline__ void accumulate_rows(float2 (&acc)[kRows], const RowSamples<DAS>& rs) {
+#pragma unroll
+    for (int k = 0; k < Step<DAS>::kRowsPerStep; ++k) {
+        float2& a = acc[K0 + k];
+        a.x += rs.e[k].x;
+        a.y += rs.e[k].y;
+        a.x = __builtin_fmaf(rs.w[k], rs.e[k].z, a.x);
+        a.y = __builtin_fmaf(rs.w[k], rs.e[k].w, a.y);
+        // pins these rows' arithmetic here, ahead of the next scheduling fence
+        asm volatile("" : "+v"(a.x), "+v"(a.y));
+    }
+}
+
+// Software pipeline over the tile's rows: while a step's samples are accumulated, the reads
+// of the next DEPTH-1 steps are in flight; a scheduling fence closes each step so that at most
+// DEPTH steps' samples are live.
+template <int K0, bool DAS, int DEPTH>
+__device__ __forceinline__ void gather_rows(float2 (&acc)[kRows], const PairDelays& d, const uint32_t* c,
+                                            RowSamples<DAS>& s0, RowSamples<DAS>& s1, const unsigned char* win) {
+    constexpr int kS = Step<DAS>::kRowsPerStep;
+    if constexpr (K0 < kRows) {
+        RowSamples<DAS> s2;
+        constexpr int kAhead = K0 + (DEPTH - 1) * kS;
+        if constexpr (kAhead < kRows) issue_rows<kAhead, DAS>(s2, d, c, win);
+        accumulate_rows<K0, DAS>(acc, s0);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (DEPTH == 3)
+            gather_rows<K0 + kS, DAS, DEPTH>(acc, d, c, s1, s2, win);
+        else
+            gather_rows<K0 + kS, DAS, DEPTH>(acc, d, c, s2, s2, win);
+    }
+}
+
+// DEPTH 3 where the registers allow it: KK with windows up to 320 entries held in flight.
+template <bool DAS, int DEPTH>
+__device__ __forceinline__ void gather_pair(float2 (&acc)[kRows], const PairDelays& d, const uint32_t* c,
+                                            const unsigned char* win) {
+    constexpr int kS = Step<DAS>::kRowsPerStep;
+    RowSamples<DAS> s0, s1;
+    issue_rows<0, DAS>(s0, d, c, win);
+    if constexpr (DEPTH == 3) issue_rows<kS, DAS>(s1, d, c, win);
+    gather_rows<0, DAS, DEPTH>(acc, d, c, s0, s1, win);
+}
+
+template <int CAP, bool DAS>
 __global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restrict__ rec,
                                                           const int32_t* __restrict__ plan,
                                                           float2* __restrict__ out, int n_arg, int m_arg,
                                                           int t_arg) {
-    using L = Lds<CAP, PB, DAS>;
-    constexpr int kPerGroup = PB / kGroups;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[L::kBytes];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[Lds<CAP>::kBytes];
     // a device plan that does not describe this call is ignored (uniform early exit)
     if (plan[PW_MAGIC] != kPlanMagic || plan[PW_KIND] != (DAS ? kPlanKindDAS : kPlanKindKK) ||
         plan[PW_N] != n_arg || plan[PW_M] != m_arg || plan[PW_T] != t_arg || plan[PW_CAP] != CAP ||
-        plan[PW_PB] != PB)
+        plan[PW_PB] != kWaves)
         return;
     PlanView pv;
     pv.T = plan[PW_T];
@@ -188,7 +262,6 @@ __global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restri
     pv.off_b = plan[PW_OFF_B];
     pv.off_lo = plan[PW_OFF_LO];
     pv.off_c = plan[PW_OFF_C];
-    pv.off_tx = plan[PW_OFF_TX];
     const int off_set = plan[PW_OFF_SET];
     const int ntiles = nxt * nzt;
     // work unit r = (set, pair share, tile)
@@ -200,119 +273,81 @@ __global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restri
     pv.xt = pv.tile - pv.zt * nxt;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int group = wave >> 2, quarter = wave & 3;
     const int set_begin = plan[off_set + s], set_end = plan[off_set + s + 1];
     const int share = (set_end - set_begin + K - 1) / K;
     const int p_begin = min(set_end, set_begin + h * share);
     const int p_end = min(set_end, p_begin + share);
+    // this wave's run of pairs
+    const int run = (p_end - p_begin + kWaves - 1) / kWaves;
+    const int w_begin = min(p_end, p_begin + wave * run);
+    const int w_end = min(p_end, w_begin + run);
 
     float2 acc[kRows];
 #pragma unroll
     for (int k = 0; k < kRows; ++k) acc[k] = make_float2(0.f, 0.f);
 
-    const float4* win = reinterpret_cast<const float4*>(lds);
-    const int32_t* aslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes);
-    const int32_t* cslot = reinterpret_cast<const int32_t*>(lds + L::kWinBytes + L::kABytes);
-
-    Prefetch<CAP> pf;
-    int q0 = p_begin;
-    int nb = batch_size<PB, DAS>(q0, p_end, pv.N);
-    if (nb > 0) {
-        load_batch<CAP, PB, DAS>(pf, rec, plan, pv, q0, nb, wave, lane);
-        store_batch<CAP, PB, DAS>(pf, lds, 0, nb, pv, q0, wave, lane);
+    float4* slot = reinterpret_cast<float4*>(lds) + wave * CAP;
+    if (w_begin < w_end) {
+        Window<CAP> wn;
+        PairDelays cur, nxt_d;
+        SlotMeta meta;
+        uint32_t c[DAS ? kRows : 1];
+        int c_elem = -1;
+        int m_base = w_begin;
+        load_meta(meta, plan, pv, m_base, w_end, lane);
+        load_pair<CAP, DAS>(wn, cur, meta, 0, rec, plan, pv, w_begin, lane);
+        fold_delays<CAP>(cur, wave);
+        store_window<CAP>(wn, slot, lane);
+        // the first pair's delays are complete before the loop, so the loop's only loads in
+        // flight during a gather are the next pair's
+        asm volatile("" ::"v"(cur.a), "v"(cur.b));
+        for (int q = w_begin; q < w_end; ++q) {
+            const bool more = q + 1 < w_end;
+            if (more) {
+                if (q + 1 - m_base == kMetaLanes) {
+                    m_base = q + 1;
+                    load_meta(meta, plan, pv, m_base, w_end, lane);
+                }
+                load_pair<CAP, DAS>(wn, nxt_d, meta, q + 1 - m_base, rec, plan, pv, q + 1, lane);
+            }
+            if constexpr (DAS) {
+                const int l = q / pv.N;
+                if (l != c_elem) {
+                    // receive delays of element l at (lane, rows): C is [L][ZPAD][XPAD]
+                    c_elem = l;
+                    const int32_t* crow =
+                        plan + pv.off_c + ((size_t)l * pv.zpad + pv.zt * kRows) * pv.xpad + pv.xt * 64;
+#pragma unroll
+                    for (int k = 0; k < kRows; ++k) c[k] = (uint32_t)crow[(unsigned)(k * pv.xpad) + (unsigned)lane];
+                }
+            }
+            gather_pair<DAS, (!DAS && CAP <= 320) ? 3 : 2>(acc, cur, c, reinterpret_cast<const unsigned char*>(lds));
+            if (more) {
+                fold_delays<CAP>(nxt_d, wave);
+                // the gather's reads of the slot precede these stores in the wave's LDS order
+                __builtin_amdgcn_sched_barrier(0);
+                store_window<CAP>(wn, slot, lane);
+                cur = nxt_d;
+            }
+        }
     }
+    // sum the waves' partial tiles in wave order
     __syncthreads();
-    int buf = 0;
-    while (nb > 0) {
-        const int q1 = q0 + nb;
-        const int nb1 = q1 < p_end ? batch_size<PB, DAS>(q1, p_end, pv.N) : 0;
-        if (nb1 > 0) load_batch<CAP, PB, DAS>(pf, rec, plan, pv, q1, nb1, wave, lane);
-        // this group's contiguous share of the batch
-        const int j0 = group * kPerGroup;
-        const int nj = min(kPerGroup, nb - j0);
-        // scalar: axial delays of the wave's rows with the window start and LDS slot folded in
-        uint32_t bs[kPerGroup][kRows];
-#pragma unroll
-        for (int jj = 0; jj < kPerGroup; ++jj) {
-            if (jj < nj) {
-                const int q = q0 + j0 + jj;
-                const int row = DAS ? plan[pv.off_tx + q] : q;
-                const int lo = plan[pv.off_lo + pv.tile * pv.P + q];
-                const uint32_t fold = (uint32_t)((buf * PB + j0 + jj) * CAP - lo) << 16;
-                const int32_t* b = plan + pv.off_b + row * pv.zpad + pv.zt * 16 + quarter * kRows;
-#pragma unroll
-                for (int k = 0; k < kRows; ++k) bs[jj][k] = (uint32_t)b[k] + fold;
-            }
-        }
-        uint32_t cq[2][kRows] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
-        int l_first = 0;
-        if constexpr (DAS) {
-            l_first = q0 / pv.N;
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int k = 0; k < kRows; ++k)
-                    cq[u][k] = (uint32_t)cslot[((buf * 2 + u) * 16 + quarter * kRows + k) * 64 + lane];
-        }
-#pragma unroll
-        for (int jj = 0; jj < kPerGroup; ++jj) {
-            if (jj < nj) {
-                const int slot = buf * PB + j0 + jj;
-                const uint32_t a = (uint32_t)aslot[slot * 64 + lane];
-                uint32_t q[kRows];
-                if constexpr (DAS) {
-                    const int u = (q0 + j0 + jj) / pv.N - l_first;
-#pragma unroll
-                    for (int k = 0; k < kRows; ++k) q[k] = a + bs[jj][k] + (u ? cq[1][k] : cq[0][k]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kRows; ++k) q[k] = a + bs[jj][k];
-                }
-#pragma unroll
-                for (int k = 0; k < kRows; ++k) {
-                    const float w = (float)(q[k] & 0xFFFFu);
-                    const float4 e = *reinterpret_cast<const float4*>(reinterpret_cast<const unsigned char*>(win) +
-                                                                      entry_byte_offset(q[k]));
-                    acc[k].x += e.x;
-                    acc[k].y += e.y;
-                    acc[k].x = __builtin_fmaf(w, e.z, acc[k].x);
-                    acc[k].y = __builtin_fmaf(w, e.w, acc[k].y);
-                }
-            }
-        }
-        if (nb1 > 0) store_batch<CAP, PB, DAS>(pf, lds, buf ^ 1, nb1, pv, q1, wave, lane);
-        __syncthreads();
-        buf ^= 1;
-        q0 = q1;
-        nb = nb1;
-    }
-    // reduce the four pair groups
     float2* red = reinterpret_cast<float2*>(lds);
-    const int slotpix = (quarter * kRows) * 64 + lane;  // + k * 64
-    if (group > 0) {
 #pragma unroll
-        for (int k = 0; k < kRows; ++k) red[(group - 1) * 1024 + slotpix + k * 64] = acc[k];
-    }
+    for (int k = 0; k < kRows; ++k) red[(wave * kRows + k) * 64 + lane] = acc[k];
     __syncthreads();
-    if (group == 0) {
-        const int x = pv.xt * 64 + lane;
-        const int z0 = pv.zt * 16 + quarter * kRows;
-        if (x < X) {
-            // unsplit: the image [S][X][Z]; split: share h of it, [K][S][X][Z]
-            float2* o = out + (((size_t)h * S + s) * X + x) * Z;
+    const int row = threadIdx.x >> 6;  // pixel (row, lane) of the tile
+    float2 v = red[row * 64 + lane];
 #pragma unroll
-            for (int k = 0; k < kRows; ++k) {
-                float2 v = acc[k];
-#pragma unroll
-                for (int g = 0; g < kGroups - 1; ++g) {
-                    const float2 t = red[g * 1024 + slotpix + k * 64];
-                    v.x += t.x;
-                    v.y += t.y;
-                }
-                if (z0 + k < Z) o[z0 + k] = v;
-            }
-        }
+    for (int w = 1; w < kWaves; ++w) {
+        const float2 t = red[(w * kRows + row) * 64 + lane];
+        v.x += t.x;
+        v.y += t.y;
     }
+    const int x = pv.xt * 64 + lane, z = pv.zt * kRows + row;
+    // unsplit: the image [S][X][Z]; split: share h of it, [K][S][X][Z]
+    if (x < X && z < Z) out[(((size_t)h * S + s) * X + x) * Z + z] = v;
 }
 
 // Sum of the K pair shares of each set (fixed order), written as the per-set images, and the
@@ -341,9 +376,7 @@ __global__ void reduce_kernel(const float2* __restrict__ part, int K, int S, int
 template <int CAP, bool DAS>
 hipError_t launch_gather(const float2* rec, const int32_t* plan_dev, float2* out, int blocks, int n, int m, int t,
                          hipStream_t st) {
-    constexpr int PB = pairs_per_batch(CAP);
-    hipLaunchKernelGGL((gather_kernel<CAP, PB, DAS>), dim3(blocks), dim3(kThreads), 0, st, rec, plan_dev, out, n, m,
-                       t);
+    hipLaunchKernelGGL((gather_kernel<CAP, DAS>), dim3(blocks), dim3(kThreads), 0, st, rec, plan_dev, out, n, m, t);
     return hipGetLastError();
 }
 
@@ -375,7 +408,7 @@ size_t gather_workspace_bytes(const int32_t* h) {
 bool gather_plan_ok(const int32_t* h, size_t plan_bytes, bool das) {
     return plan_bytes >= (size_t)PW_HEADER_WORDS * 4 && h[PW_MAGIC] == kPlanMagic &&
            h[PW_KIND] == (das ? kPlanKindDAS : kPlanKindKK) && (size_t)h[PW_TOTAL] * 4 <= plan_bytes &&
-           h[PW_PB] == pairs_per_batch(h[PW_CAP]) && h[PW_SPLIT] >= 1 && h[PW_SPLIT] <= kMaxSplit;
+           h[PW_PB] == pairs_per_batch(h[PW_CAP]) && h[PW_PB] == kWaves && h[PW_SPLIT] >= 1 && h[PW_SPLIT] <= kMaxSplit;
 }
 
 // Gather into the images (unsplit) or into the share buffer followed by the reduction; the

@@ -23,14 +23,9 @@ constexpr int32_t kTargetWorkgroups = 256;  // one per CU of an MI355X
 constexpr int32_t kCaps[] = {64, 128, 192, 256, 320, 384, 448, 512};
 constexpr int32_t kNumCaps = 8;
 
-// Pairs staged per batch for a given capacity: two LDS buffers of pairs_per_batch slots,
-// each slot holding cap 16-byte entries plus the folded lateral (64) and axial (16) delays,
-// within a 144 KiB budget; a multiple of the 4 pair groups of a workgroup.
-constexpr int32_t pairs_per_batch(int32_t cap) {
-    return ((147456 / 2) / (cap * 16 + kTileX * 4 + kTileZ * 4)) / 4 * 4 > 32
-               ? 32
-               : ((147456 / 2) / (cap * 16 + kTileX * 4 + kTileZ * 4)) / 4 * 4;
-}
+// Pairs in flight per workgroup: one per wave, each wave owning one LDS window slot of cap
+// 16-byte entries (at most 16 x 512 x 16 B = 128 KiB).
+constexpr int32_t pairs_per_batch(int32_t cap) { return cap > 0 ? 16 : 0; }
 
 enum PlanWord : int32_t {
     PW_MAGIC = 0,
@@ -48,14 +43,14 @@ enum PlanWord : int32_t {
     PW_ZPAD,       // n_zt * 16
     PW_CAP,        // slot capacity (entries) of the kernel variant
     PW_MAXW,       // largest window any (pair, tile) needs
-    PW_PB,         // pairs per batch
+    PW_PB,         // pairs in flight per workgroup (one per wave)
     PW_OFF_SET,    // int32[S+1]   first pair of each set (pairs grouped by set)
     PW_OFF_REC,    // int32[P]     record index: i*M + o (KK), i*L + l (DAS)
     PW_OFF_A,      // int32[P or N][XPAD]  folded lateral delay (Q16.16, includes t0)
     PW_OFF_B,      // int32[P or N][ZPAD]  folded axial delay
     PW_OFF_LO,     // int32[n_tiles][P]    first record sample of each window
     PW_OFF_C,      // DAS: int32[L][ZPAD][XPAD] receive delay, x fastest; KK: 0
-    PW_OFF_TX,     // DAS: int32[P] transmit index of pair p (A/B row); KK: pair index p
+    PW_OFF_TX,     // DAS: int32[P] transmit index of pair p = l N + i (A/B row i); KK: pair index p
     PW_TOTAL,      // plan length in words
     PW_SPLIT,      // pair shares per (set, tile): workgroups = tiles * S * SPLIT
     PW_HEADER_WORDS = 32

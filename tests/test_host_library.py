@@ -197,7 +197,7 @@ def _check_kk_plan(plan, sel, ora, w):
     cap, pb = h["CAP"], h["PB"]
     assert h["MAXW"] <= cap and cap % 64 == 0 and pb % 4 == 0 and pb >= 4
     # LDS footprint of the kernel variant (two buffers of pb slots)
-    assert 2 * pb * (cap * 16 + 64 * 4 + 16 * 4) <= 147456 and 2 * pb * cap < 65536
+    assert pb == 16 and pb * cap * 16 <= 131072 and pb * cap < 65536
     sets = plan[h["OFF_SET"]:h["OFF_SET"] + S + 1]
     assert sets[0] == 0 and sets[-1] == P and np.all(np.diff(sets) > 0)
     order = [p for s in range(S) for p in range(P) if sel["pairs"][p][2] == s]
