@@ -6,12 +6,13 @@
 //      W_k[o][l] = exp(2 pi i r / (n 2^22)), r = (k shift[o][l]) mod (n 2^22), on MFMA
 //      (v_mfma_f32_32x32x2_f32: one complex element l per instruction, 16 receive angles x
 //      {Re, Im} rows by 32 transmit columns; 8 bins per workgroup, one per wave, the spectrum
-//      staged through LDS 16 elements at a time);
+//      staged through LDS 16 elements at a time in a software pipeline across chunks);
 //   3. inverse FFT of each (i, o) spectrum, first T samples.
 // The phase is formed exactly in integers; only the reduced fraction becomes floating point:
-// W = E[r >> 22] * exp(2 pi i (r mod 2^22) / (n 2^22)), with E[m] = exp(2 pi i m / n) tabulated
-// per workgroup from two FP64-evaluated factors and the small second factor (|angle| < 2 pi / n)
-// by its Taylor series.
+// W = E[r >> 22] * exp(2 pi i (r mod 2^22) / (n 2^22)), with E[m] = exp(2 pi i m / n) the
+// product of two FP64-evaluated factor tables and the small second factor (|angle| < 2 pi / n)
+// by its Taylor series.  Within a bin block only the first bin's phase and the one-bin step are
+// evaluated so; the other bins are products of the step's powers (a few roundings deep).
 // Also the DAS comparator entry point (analytic channel data + delay-gather).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -28,7 +29,11 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 constexpr int kContractWaves = kBinBlock;   // one bin of the block per wave
 constexpr int kContractThreads = kContractWaves * 64;
 constexpr int kChunkL = 16;                  // elements per LDS chunk
-constexpr int kRowFloats = kChunkL * kBinBlock * 2 + 4;  // one transmit column + pad (16-byte rows)
+// One transmit column of a chunk plus a pad of two floats: rows stay 8-byte aligned and
+// column c's operand reads land on banks 2c, 2c+1, so a wave's 32 columns x {Re, Im} hit all
+// 64 banks once.
+constexpr int kRowFloats = kChunkL * kBinBlock * 2 + 2;
+constexpr int kStages = 4;                   // chunks whose global loads are in flight
 
 // exp(+2 pi i ((k s) mod (n 2^22)) / (n 2^22)) for 0 <= k < 2^23, any int32 s: the turn count
 // is reduced exactly with 24-bit products (k s = k s_hi 2^22 + k s_lo, s_lo < 2^22), the coarse
@@ -51,6 +56,10 @@ __device__ __forceinline__ float2 shear_phase(uint32_t k, int32_t s, const float
     return make_float2(e.x * cf - e.y * sf, e.x * sf + e.y * cf);
 }
 
+__device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
 // exp(+2 pi i m / n) = exp(2 pi i (m >> (log2n - 6)) / 64) exp(2 pi i (m mod n/64) / n): the
 // two factor tables, evaluated in FP64
 template <int LOG2N>
@@ -64,12 +73,14 @@ __device__ __forceinline__ void build_phase_factors(float2* fac, int tid) {
 }
 
 // Global loads of one chunk: spectrum X[kb][i][l0 .. l0+15][0..7] (a contiguous 1 KiB run per
-// transmit column i) and the shifts of 4 (receive angle, element) entries per thread.
+// transmit column i) and the shift of this thread's (receive angle, element) entry.
 struct ContractStage {
     float4 v[4];
-    int32_t s[4];
+    int32_t s;
 };
 
+// Every path issues the same loads (clamped to valid addresses; out-of-range entries are
+// zeroed at the store), so the wait before a stage's store can leave the later stages in flight.
 __device__ __forceinline__ void contract_load(ContractStage& st, const float2* __restrict__ X,
                                               const int32_t* __restrict__ shift, int kb, int ncol, int ct, int L,
                                               int l0, int M, int rt, int tid) {
@@ -77,18 +88,17 @@ __device__ __forceinline__ void contract_load(ContractStage& st, const float2* _
     for (int u = 0; u < 4; ++u) {
         const int f = tid + u * kContractThreads;  // float4 index in the 32 x 64 chunk
         const int i = f >> 6, j = f & 63;          // column, float4 within the column's run
-        const int l = l0 + (j >> 2);
-        st.v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (l < L)
-            st.v[u] = reinterpret_cast<const float4*>(X + (((size_t)kb * ncol + ct * 32 + i) * L + l) * kBinBlock)[j & 3];
-        // phase entry e = (l_local, bin, angle) of this thread: angle fastest
-        const int e = tid + u * kContractThreads;
-        const int ol = e & 15, ll = e >> 7;
-        const int o = rt * 16 + ol;
-        st.s[u] = (o < M && l0 + ll < L) ? shift[(size_t)o * L + l0 + ll] : 0;
+        const int l = min(l0 + (j >> 2), L - 1);
+        st.v[u] = reinterpret_cast<const float4*>(X + (((size_t)kb * ncol + ct * 32 + i) * L + l) * kBinBlock)[j & 3];
     }
+    const int o = min(rt * 16 + (tid & 15), M - 1), l = min(l0 + ((tid >> 4) & 15), L - 1);
+    st.s = shift[(size_t)o * L + l];  // used by threads 0..255, (angle, element) = (tid % 16, tid / 16)
 }
 
+// Spectrum rows into LDS, and the phases W[l][bin][angle] of the chunk: thread (angle, l) of
+// the first four waves evaluates the phase of the block's first bin exactly and the one-bin
+// step D = exp(2 pi i s / (n 2^22)), and forms the other seven bins as products of D, D^2 and
+// D^4 (at most five roundings deep).
 template <int LOG2N>
 __device__ __forceinline__ void contract_store(const ContractStage& st, float* xs, float2* ws, const float2* fac,
                                                int kb, int l0, int L, int M, int rt, int tid) {
@@ -96,35 +106,56 @@ __device__ __forceinline__ void contract_store(const ContractStage& st, float* x
     for (int u = 0; u < 4; ++u) {
         const int f = tid + u * kContractThreads;
         const int i = f >> 6, j = f & 63;
-        *reinterpret_cast<float4*>(xs + i * kRowFloats + j * 4) = st.v[u];
-        const int e = tid + u * kContractThreads;
-        const int ol = e & 15, bin = (e >> 4) & 7, ll = e >> 7;
+        const bool in = l0 + (j >> 2) < L;
+        float2* row = reinterpret_cast<float2*>(xs + i * kRowFloats + j * 4);
+        row[0] = in ? make_float2(st.v[u].x, st.v[u].y) : make_float2(0.f, 0.f);
+        row[1] = in ? make_float2(st.v[u].z, st.v[u].w) : make_float2(0.f, 0.f);
+    }
+    if (tid < 256) {  // waves 0..3
+        const int ol = tid & 15, ll = tid >> 4;
         const bool valid = rt * 16 + ol < M && l0 + ll < L;
-        const float2 w = shear_phase<LOG2N>((uint32_t)(kb * kBinBlock + bin), st.s[u], fac);
-        ws[e] = valid ? w : make_float2(0.f, 0.f);
+        const float2 w0 = shear_phase<LOG2N>((uint32_t)(kb * kBinBlock), st.s, fac);
+        const float2 d1 = shear_phase<LOG2N>(1u, st.s, fac);
+        const float2 d2 = cmul2(d1, d1), d4 = cmul2(d2, d2);
+        const float2 w1 = cmul2(w0, d1), w2 = cmul2(w0, d2), w3 = cmul2(w1, d2);
+        const float2 w[8] = {w0, w1, w2, w3, cmul2(w0, d4), cmul2(w1, d4), cmul2(w2, d4), cmul2(w3, d4)};
+        const float2 zero = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int b = 0; b < kBinBlock; ++b) ws[(ll * kBinBlock + b) * 16 + ol] = valid ? w[b] : zero;
     }
 }
 
-// the 16 MFMAs of one chunk: operands for every element read first, then the chain
-template <int LOG2N>
-__device__ __forceinline__ void contract_mfma(floatx16& acc, const float* xs, const float2* ws, int col, int wave,
+// MFMA operands of one chunk for one lane: the spectrum value (B) and the phase component (A,
+// sign applied) of each of the chunk's 16 elements.
+struct ChunkOperands {
+    float a[kChunkL];
+    float b[kChunkL];
+};
+
+__device__ __forceinline__ void read_operands(ChunkOperands& op, const float* xs, const float2* ws, int col, int wave,
                                               int part, int orow, int comp, uint32_t negmask) {
     const float* xrow = xs + col * kRowFloats + wave * 2 + part;
     const float* wrow = reinterpret_cast<const float*>(ws) + (wave * 16 + orow) * 2 + comp;
-    float av[kChunkL], bv[kChunkL];
 #pragma unroll
     for (int ll = 0; ll < kChunkL; ++ll) {
-        bv[ll] = xrow[ll * kBinBlock * 2];
-        av[ll] = wrow[ll * kBinBlock * 16 * 2];
-    }
-    __builtin_amdgcn_sched_barrier(0);  // keep all 32 operand reads in flight ahead of the MFMA chain
-#pragma unroll
-    for (int ll = 0; ll < kChunkL; ++ll) {
-        const float a = __uint_as_float(__float_as_uint(av[ll]) ^ negmask);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bv[ll], acc, 0, 0, 0);
+        op.b[ll] = xrow[ll * kBinBlock * 2];
+        op.a[ll] = __uint_as_float(__float_as_uint(wrow[ll * kBinBlock * 16 * 2]) ^ negmask);
     }
 }
 
+// the 16 MFMAs of one chunk, in two interleaved accumulation chains (even and odd elements)
+__device__ __forceinline__ void chunk_mfma(floatx16 (&acc)[2], const ChunkOperands& op) {
+#pragma unroll
+    for (int ll = 0; ll < kChunkL; ++ll)
+        acc[ll & 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(op.a[ll], op.b[ll], acc[ll & 1], 0, 0, 0);
+}
+
+// Per bin block (8 bins, one per wave), receive-angle tile of 16 and transmit tile of 32:
+// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] over all elements in chunks of 16.  Software pipeline
+// across chunks, one workgroup barrier per chunk: while the MFMAs of chunk c run from
+// registers, the operands of chunk c+1 are read from LDS and chunk c+2 (spectrum rows and its
+// phases) is written to LDS from its register stage, whose global loads were issued kStages-2
+// chunks earlier.  The results leave through LDS as 64-byte runs (8 bins of one (i, o)).
 template <int LOG2N>
 __global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
                                                                      const int32_t* __restrict__ shift,
@@ -148,40 +179,56 @@ __global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2
     const int comp = (ytype == part) ? 0 : 1;
     const uint32_t negmask = (ytype == 0 && part == 1) ? 0x80000000u : 0u;
 
-    floatx16 acc;
+    floatx16 acc[2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    for (int v = 0; v < 16; ++v) acc[0][v] = acc[1][v] = 0.0f;
 
-    // chunks c + 1 and c + 2 are in flight (two register stages) while chunk c is multiplied
-    ContractStage st[2];
-    const int nchunks = (L + kChunkL - 1) / kChunkL;
-    contract_load(st[0], X, shift, kb, ncol, ct, L, 0, M, rt, tid);
-    if (nchunks > 1) contract_load(st[1], X, shift, kb, ncol, ct, L, kChunkL, M, rt, tid);
+    // a whole number of pipeline rounds: chunks past the last element are all zero
+    const int nchunks = (L + kChunkL * kStages - 1) / (kChunkL * kStages) * kStages;
+    ContractStage st[kStages];
+    ChunkOperands op[2];
+#pragma unroll
+    for (int u = 0; u < kStages; ++u) contract_load(st[u], X, shift, kb, ncol, ct, L, u * kChunkL, M, rt, tid);
     __syncthreads();  // phase factors complete
     contract_store<LOG2N>(st[0], xs[0], ws[0], fac, kb, 0, L, M, rt, tid);
+    contract_load(st[0], X, shift, kb, ncol, ct, L, kStages * kChunkL, M, rt, tid);
+    contract_store<LOG2N>(st[1], xs[1], ws[1], fac, kb, kChunkL, L, M, rt, tid);
+    contract_load(st[1], X, shift, kb, ncol, ct, L, (kStages + 1) * kChunkL, M, rt, tid);
     __syncthreads();
-    for (int c = 0; c < nchunks; c += 2) {
-        // even chunk c from buffer 0 (stage 1 holds c + 1, stage 0 is free)
-        if (c + 2 < nchunks) contract_load(st[0], X, shift, kb, ncol, ct, L, (c + 2) * kChunkL, M, rt, tid);
-        contract_mfma<LOG2N>(acc, xs[0], ws[0], col, wave, part, orow, comp, negmask);
-        if (c + 1 < nchunks) contract_store<LOG2N>(st[1], xs[1], ws[1], fac, kb, (c + 1) * kChunkL, L, M, rt, tid);
-        __syncthreads();
-        if (c + 1 >= nchunks) break;
-        // odd chunk c + 1 from buffer 1 (stage 0 holds c + 2, stage 1 is free)
-        if (c + 3 < nchunks) contract_load(st[1], X, shift, kb, ncol, ct, L, (c + 3) * kChunkL, M, rt, tid);
-        contract_mfma<LOG2N>(acc, xs[1], ws[1], col, wave, part, orow, comp, negmask);
-        if (c + 2 < nchunks) contract_store<LOG2N>(st[0], xs[0], ws[0], fac, kb, (c + 2) * kChunkL, L, M, rt, tid);
-        __syncthreads();
+    read_operands(op[0], xs[0], ws[0], col, wave, part, orow, comp, negmask);
+    __syncthreads();  // every wave has chunk 0's operands before buffer 0 takes chunk 2
+    for (int c0 = 0; c0 < nchunks; c0 += kStages) {
+#pragma unroll
+        for (int u = 0; u < kStages; ++u) {
+            const int c = c0 + u;  // chunk c: operands in op[u & 1]; c+1 in LDS buffer (u+1)&1
+            chunk_mfma(acc, op[u & 1]);
+            read_operands(op[(u + 1) & 1], xs[(u + 1) & 1], ws[(u + 1) & 1], col, wave, part, orow, comp, negmask);
+            const int s2 = (u + 2) % kStages;  // register stage of chunk c+2 (static once unrolled)
+            // chunk c+2 over chunk c's LDS buffer (read before the previous barrier), then the
+            // freed stage takes chunk c+2+kStages (loads past the end re-read valid addresses)
+            contract_store<LOG2N>(st[s2], xs[u & 1], ws[u & 1], fac, kb, (c + 2) * kChunkL, L, M, rt, tid);
+            contract_load(st[s2], X, shift, kb, ncol, ct, L, (c + 2 + kStages) * kChunkL, M, rt, tid);
+            __syncthreads();
+        }
     }
-    const int i = ct * 32 + col;
-    const int k = kb * kBinBlock + wave;
-    if (i >= ntx) return;
-    // accumulator v of lane holds row (v/4)*8 + (lane/32)*4 + v%4, column lane%32; rows v and
-    // v + 8 are Re and Im of the same receive angle
+    // results to LDS as runs [i][o][bin] (i stride 129 float2, so a half-wave's 32 columns
+    // write 64 distinct banks), then out as 64-byte runs, 8 threads per run
+    constexpr int kYCol = 16 * kBinBlock + 1;
+    static_assert(32 * kYCol * 8 <= (int)sizeof(xs), "result staging fits the spectrum buffers");
+    float2* yst = reinterpret_cast<float2*>(&xs[0][0]);
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-        const int oo = rt * 16 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        if (oo < M) Y[((size_t)i * M + oo) * kpad + k] = make_float2(acc[v], acc[v + 8]);
+        const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        yst[col * kYCol + ol * kBinBlock + wave] = make_float2(acc[0][v] + acc[1][v], acc[0][v + 8] + acc[1][v + 8]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int f = tid + u * kContractThreads;  // float2 f & 7 of run f >> 3
+        const int run = f >> 3, q = f & 7;
+        const int il = run >> 4, ol = run & 15;
+        const int i = ct * 32 + il, o = rt * 16 + ol;
+        if (i < ntx && o < M) Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q] = yst[il * kYCol + ol * kBinBlock + q];
     }
 }
 
