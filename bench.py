@@ -14,10 +14,14 @@ compounding.  Selection, delay tables and plans are per-geometry setup, built be
 (as the paper's Table II excludes them).  Printed: one JSON line.
   value            pixel*pair / s of the whole frame (X Z P / step time), in Gpixel*pair/s
   frames_per_s     KK frames per second;  das_frames_per_s  DAS (Eq. 4) on the same data
-  roofline         gather kernel against the VALU issue bound
+  roofline         the gather kernel (Eq. 5, the step the metric counts) against the VALU issue
+                   bound; traffic from the committed PMC byte-counter summary when it matches
+                   the kernel source, else null
+  stage_rooflines  every stage of the frame against its own bound, from live stage timings
   cpu_baseline     the FP64 oracle, unmodified, on a bounded sample on this host
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -29,10 +33,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KK beamform Gpixel·pair/s and frames/s vs GPU DAS at rel-L2 ≤1e-5 (FP32)"
 # VALU issue rate of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz lane-operations per second,
-# and the algorithmic lane-operations per pixel*pair of the gather (delay add, index
-# extraction, weight conversion, complex interpolate-accumulate with a stored difference).
+# and the algorithmic lane-operations per pixel*pair of a delay-gather: one delay add, two for
+# index and fraction, four for the complex interpolate-accumulate, one address operation.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-OPS_PER_PIXEL_PAIR = 7
+OPS_PER_PIXEL_PAIR = 8
+HBM_BYTES_PER_S = 8.0e12
+MFMA_FP32_FLOPS = 157.3e12
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gather_vernier_traffic.md")
+GATHER_SOURCE = os.path.join(ROOT, "paper_2603_22496_amd", "csrc", "kk_beamform.hip")
+
+
+def measured_gather_traffic():
+    """HBM bytes per gather launch from the committed byte-counter summary, or None when the
+    kernel source has changed since the counters were taken."""
+    try:
+        vals = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if "=" in line:
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+        src = hashlib.sha256(open(GATHER_SOURCE, "rb").read()).hexdigest()
+        if vals.get("source_sha256") != src:
+            return None
+        return int(float(vals["gather_traffic_bytes"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -40,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-frames", type=int, default=10, help="oracle frames timed for cpu_baseline (0: skip)")
     ap.add_argument("--no-das", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle check of the timed frame")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -163,6 +188,26 @@ def main():
     gather_rate = pixpair / (ms_gather * 1e-3)
     achieved = OPS_PER_PIXEL_PAIR * gather_rate / 1e12
     peak = VALU_LANE_OPS / 1e12
+    # stage rooflines: algorithmic bytes or work of each stage over its live time
+    K = su.tpad // 2 + 1
+    rec_bytes = w.N * w.L * w.T * 2                     # int16 channel data
+    spec_bytes = w.N * w.L * K * 8                      # analytic spectra (materialised)
+    y_bytes = w.N * su.M * K * 8                        # sheared spectra
+    rt_bytes = w.N * su.M * w.T * 8                     # RF_theta records
+    dec_unfused = rec_bytes + 2 * spec_bytes + 2 * y_bytes + rt_bytes
+    dec_fused = rec_bytes + rt_bytes
+    dec_flops = 8.0 * su.M * w.L * w.N * K
+    t_dec = ms_dec * 1e-3
+    stage_roofs = {
+        "decompose": {"bound": "hbm", "time_us": round(ms_dec * 1e3, 2),
+                      "bytes_unfused": dec_unfused, "frac_unfused": round(dec_unfused / HBM_BYTES_PER_S / t_dec, 4),
+                      "bytes_fused_minimum": dec_fused,
+                      "frac_fused_minimum": round(dec_fused / HBM_BYTES_PER_S / t_dec, 4),
+                      "mfma_flops": dec_flops, "frac_mfma": round(dec_flops / MFMA_FP32_FLOPS / t_dec, 4)},
+        "beamform": {"bound": "alu", "time_us": round(ms_gather * 1e3, 2),
+                     "lane_ops": OPS_PER_PIXEL_PAIR * pixpair,
+                     "frac": round(OPS_PER_PIXEL_PAIR * pixpair / VALU_LANE_OPS / (ms_gather * 1e-3), 4)},
+    }
     out = {
         "metric": METRIC,
         "value": round(pixpair / (ms * 1e-3) / 1e9, 2),
@@ -193,11 +238,17 @@ def main():
             "peak": round(peak, 3),
             "unit": "TOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": measured_gather_traffic(),
             "ops_per_pixel_pair": OPS_PER_PIXEL_PAIR,
+            "pixel_pairs_per_launch": pixpair,
         },
+        "stage_rooflines": stage_roofs,
     }
     if "das_ms" in res:
+        das_units = w.X * w.Z * w.N * w.L                 # pixel x (transmit, element) gathers
+        out["stage_rooflines"]["das"] = {
+            "bound": "alu", "time_us": round(res["das_ms"] * 1e3, 2), "lane_ops": OPS_PER_PIXEL_PAIR * das_units,
+            "frac": round(OPS_PER_PIXEL_PAIR * das_units / VALU_LANE_OPS / (res["das_ms"] * 1e-3), 4)}
         out["das_frames_per_s"] = round(1e3 / res["das_ms"], 1)
         out["stages_us"]["das"] = round(res["das_ms"] * 1e3, 2)
         out["kk_over_das_speedup"] = round(res["das_ms"] / ms, 2)
