@@ -6,9 +6,11 @@
 // radix-2/4 stages with exact internal constants) and one radix-2/4/8 pass for the remainder,
 // 256 threads per transform.  The first pass reads global memory directly (coalesced), every
 // later pass goes through one LDS round trip (the LDS array carries one pad slot per 16 points
-// so the strided writes of a radix-16 pass spread over the banks).  A twiddle
-// exp(-2 pi i m / n) is the product of two factors, exp(-2 pi i (m >> (log2n-6)) / 64) and
-// exp(-2 pi i (m mod n/64) / n), each evaluated in FP64 by the workgroup into a small LDS table.
+// so the strided writes of a radix-16 pass spread over the banks).  The twiddles of a butterfly,
+// W^(r k) for r = 1 .. R-1, come from one base twiddle W^k by a power tree (W^r = W^(r/2) W^(r -
+// r/2), at most four products deep); the base twiddle exp(-2 pi i m / n) is the product of two
+// factors, exp(-2 pi i (m >> (log2n-6)) / 64) and exp(-2 pi i (m mod n/64) / n), each evaluated in
+// FP64 by the workgroup into a small LDS table.
 // Forward transforms take two real int16 records per workgroup as the real and imaginary parts of one complex sequence and unpack them straight into the two masked
 // analytic spectra: for 0 < k < n/2, A[k] = Z[k] + conj(Z[n-k]) and
 // B[k] = -i (Z[k] - conj(Z[n-k])) (the x2 of the analytic mask absorbs the 1/2 of the unpack);
@@ -118,6 +120,21 @@ struct Dft<16, INV> {
 
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
+// Padded LDS positions of a butterfly's R inputs (b + r NB) and outputs (out_index(b, r)) as a
+// per-butterfly base plus a constant step in r (NB and NS are 1 or multiples of 16 and R
+// divides 16, so the pad term splits exactly).
+template <int N, int R>
+__device__ __forceinline__ int read_base(int b) { return pad(b); }
+template <int N, int R>
+constexpr int read_step() { return (N / R) + (N / R) / 16; }
+template <int N, int R, int NS>
+__device__ __forceinline__ int write_base(int b) {
+    if constexpr (NS == 1) return pad(b * R);
+    else return pad((b / NS) * NS * R + (b % NS));
+}
+template <int N, int R, int NS>
+constexpr int write_step() { return NS == 1 ? 1 : NS + NS / 16; }
+
 // the two twiddle factor tables: fac[0..63] coarse, fac[64..64+n/64) fine
 template <int LOG2N>
 __device__ __forceinline__ void make_factors(float2* fac, int tid) {
@@ -145,18 +162,20 @@ struct FftPlan {
     static constexpr int ns(int p) { return p == 0 ? 1 : ns(p - 1) * radix(p - 1); }
 };
 
-// twiddles of butterfly b in a pass with NS already-combined points: v[r] *= W_{NS R}^{r k}
+// twiddles of butterfly b in a pass with NS already-combined points: v[r] *= W_{NS R}^{r k},
+// the powers W^r of the base twiddle by a product tree
 template <int LOG2N, int R, int NS, bool INV>
 __device__ __forceinline__ void twiddle(float2* v, int b, const float2* fac) {
     constexpr int N = 1 << LOG2N;
     if constexpr (NS > 1) {
         const int k = b % NS;
         constexpr int step = N / (NS * R);
+        float2 w[R];
+        w[1] = twiddle_of<LOG2N>(fac, k * step);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-            const float2 w = twiddle_of<LOG2N>(fac, r * k * step);
-            v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
-        }
+        for (int r = 2; r < R; ++r) w[r] = cmul(w[r / 2], w[r - r / 2]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
     }
 }
 
@@ -178,7 +197,7 @@ __device__ __forceinline__ void pass_lds(float2* data, const float2* fac, int ti
         const int b = tid + p * kFftThreads;
         if (b < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[p][r] = data[pad(b + r * NB)];
+            for (int r = 0; r < R; ++r) v[p][r] = data[read_base<N, R>(b) + r * read_step<N, R>()];
             twiddle<LOG2N, R, NS, INV>(v[p], b, fac);
             Dft<R, INV>::run(v[p]);
         }
@@ -189,7 +208,7 @@ __device__ __forceinline__ void pass_lds(float2* data, const float2* fac, int ti
         const int b = tid + p * kFftThreads;
         if (b < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) data[pad(out_index<N, R, NS>(b, r))] = v[p][r];
+            for (int r = 0; r < R; ++r) data[write_base<N, R, NS>(b) + r * write_step<N, R, NS>()] = v[p][r];
         }
     }
     __syncthreads();
@@ -204,100 +223,72 @@ __device__ __forceinline__ void middle_passes(float2* data, const float2* fac, i
     }
 }
 
-// int16 samples of one record pair as consumed by the first radix-16 pass
-template <int LOG2N>
-struct PairSamples {
-    static constexpr int N = 1 << LOG2N;
-    static constexpr int NB = N / 16;
-    static constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
-    short a[PER][16];
-    short b[PER][16];
-};
-
-template <int LOG2N>
-__device__ __forceinline__ void load_pair(PairSamples<LOG2N>& ps, const int16_t* __restrict__ rf, int pair,
-                                          int ntraces, int T, int tid) {
-    using PS = PairSamples<LOG2N>;
-    const int t0 = 2 * pair, t1 = t0 + 1;
-    const bool has1 = t1 < ntraces;
-    const int16_t* a = rf + (size_t)t0 * T;
-    const int16_t* b = rf + (size_t)(has1 ? t1 : t0) * T;
-#pragma unroll
-    for (int p = 0; p < PS::PER; ++p) {
-        const int bb = tid + p * kFftThreads;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int n = bb + r * PS::NB;
-            const bool ok = bb < PS::NB && n < T;
-            ps.a[p][r] = ok ? a[n] : (short)0;
-            ps.b[p][r] = (ok && has1) ? b[n] : (short)0;
-        }
-    }
-}
-
-// Grid-stride over record pairs; the next pair's samples are loaded into registers while the
-// current pair is transformed.
+// One record pair per workgroup: the two real records are the real and imaginary parts of one
+// complex FFT.  The records enter LDS as 16-byte loads (8 samples), zero-padded to n; the
+// spectra leave as one 64-byte run (8 bins) per thread and record.
 template <int LOG2N, bool BLOCKED>
 __global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
                                                                   int T, float2* __restrict__ out, int L, int ncol,
                                                                   int kpad) {
     using F = FftPlan<LOG2N>;
-    using PS = PairSamples<LOG2N>;
     constexpr int N = F::N;
-    static_assert(F::radix(0) == 16, "first pass is radix 16");
-    __shared__ float2 data[N + N / 16];
+    __shared__ __attribute__((aligned(16))) float2 data[N + N / 16];
     __shared__ float2 fac[64 + N / 64];
     const int tid = threadIdx.x;
-    const int npairs = (ntraces + 1) / 2;
+    const int t0 = 2 * blockIdx.x, t1 = t0 + 1;
+    const bool has1 = t1 < ntraces;
     make_factors<LOG2N>(fac, tid);
-    PS cur, nxt;
-    int pair = blockIdx.x;
-    if (pair < npairs) load_pair<LOG2N>(cur, rf, pair, ntraces, T, tid);
-    for (; pair < npairs; pair += gridDim.x) {
-        const int next = pair + gridDim.x;
-        if (next < npairs) load_pair<LOG2N>(nxt, rf, next, ntraces, T, tid);
-        const int t0 = 2 * pair, t1 = t0 + 1;
-        const bool has1 = t1 < ntraces;
+    const int16_t* a = rf + (size_t)t0 * T;
+    const int16_t* b = rf + (size_t)(has1 ? t1 : t0) * T;
+    if ((T & 7) == 0) {  // 8-sample groups: 16-byte aligned (records start at multiples of 16 B)
+        for (int g = tid; g < N / 8; g += kFftThreads) {
+            const int n0 = g * 8;
+            int16_t xa[8], xb[8];
+            if (n0 < T) {
+                *reinterpret_cast<uint4*>(xa) = *reinterpret_cast<const uint4*>(a + n0);
+                *reinterpret_cast<uint4*>(xb) = *reinterpret_cast<const uint4*>(b + n0);
+            } else {
 #pragma unroll
-        for (int p = 0; p < PS::PER; ++p) {  // first pass from registers
-            const int bb = tid + p * kFftThreads;
-            if (bb < PS::NB) {
-                float2 v[16];
+                for (int j = 0; j < 8; ++j) xa[j] = xb[j] = 0;
+            }
+            float2* d = data + pad(n0);  // 8 consecutive entries, no pad slot inside
 #pragma unroll
-                for (int r = 0; r < 16; ++r) v[r] = make_float2((float)cur.a[p][r], (float)cur.b[p][r]);
-                Dft<16, false>::run(v);
+            for (int j = 0; j < 8; ++j) d[j] = make_float2((float)xa[j], has1 ? (float)xb[j] : 0.f);
+        }
+    } else {
+        for (int n = tid; n < N; n += kFftThreads)
+            data[pad(n)] = make_float2(n < T ? (float)a[n] : 0.f, (n < T && has1) ? (float)b[n] : 0.f);
+    }
+    __syncthreads();
+    middle_passes<LOG2N, 0, false>(data, fac, tid);
+    pass_lds<LOG2N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, fac, tid);
+    // unpack the two real spectra with the analytic mask, two bins (16 bytes) per thread and
+    // record: four neighbouring threads complete one 64-byte run of 8 bins
+    const int i0 = t0 / L, l0 = t0 - i0 * L, i1 = t1 / L, l1 = t1 - i1 * L;
+    float2* o0 = BLOCKED ? out + ((size_t)i0 * L + l0) * kBinBlock : out + (size_t)t0 * kpad;
+    float2* o1 = BLOCKED ? out + ((size_t)i1 * L + l1) * kBinBlock : out + (size_t)t1 * kpad;
+    const unsigned kstride = BLOCKED ? (unsigned)(ncol * L * kBinBlock) : (unsigned)kBinBlock;  // between runs
+    for (int kp = tid; 2 * kp < kpad; kp += kFftThreads) {
+        float2 A[2], B[2];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) data[pad(out_index<N, 16, 1>(bb, r))] = v[r];
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * kp + h;
+            A[h] = B[h] = make_float2(0.f, 0.f);
+            if (k <= N / 2) {
+                const float2 zk = data[pad(k)];
+                const float2 zm = data[pad((N - k) & (N - 1))];
+                if (k == 0 || k == N / 2) {
+                    A[h] = make_float2(zk.x, 0.f);
+                    B[h] = make_float2(zk.y, 0.f);
+                } else {
+                    A[h] = make_float2(zk.x + zm.x, zk.y - zm.y);
+                    B[h] = make_float2(zk.y + zm.y, zm.x - zk.x);
+                }
             }
         }
-        __syncthreads();
-        middle_passes<LOG2N, 1, false>(data, fac, tid);
-        pass_lds<LOG2N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, fac, tid);
-        // unpack the two real spectra with the analytic mask
-        const int i0 = t0 / L, l0 = t0 - i0 * L, i1 = t1 / L, l1 = t1 - i1 * L;
-        for (int k = tid; k <= N / 2; k += kFftThreads) {
-            const float2 zk = data[pad(k)];
-            const float2 zm = data[pad((N - k) & (N - 1))];
-            float2 A, B;
-            if (k == 0 || k == N / 2) {
-                A = make_float2(zk.x, 0.f);
-                B = make_float2(zk.y, 0.f);
-            } else {
-                A = make_float2(zk.x + zm.x, zk.y - zm.y);
-                const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
-                B = make_float2(d.y, -d.x);
-            }
-            if (BLOCKED) {
-                const size_t kb = (size_t)(k >> 3), kk = (size_t)(k & 7);
-                out[(((kb * ncol + i0) * L + l0) << 3) + kk] = A;
-                if (has1) out[(((kb * ncol + i1) * L + l1) << 3) + kk] = B;
-            } else {
-                out[(size_t)t0 * kpad + k] = A;
-                if (has1) out[(size_t)t1 * kpad + k] = B;
-            }
-        }
-        __syncthreads();  // the next pair overwrites data
-        cur = nxt;
+        const unsigned off = (unsigned)(kp >> 2) * kstride + (unsigned)(2 * (kp & 3));
+        *reinterpret_cast<float4*>(o0 + off) = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
+        if (has1) *reinterpret_cast<float4*>(o1 + off) = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
     }
 }
 
@@ -352,7 +343,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
                 }
                 Dft<R, true>::run(v);
 #pragma unroll
-                for (int r = 0; r < R; ++r) data[pad(out_index<N, R, 1>(bb, r))] = v[r];
+                for (int r = 0; r < R; ++r) data[write_base<N, R, 1>(bb) + r * write_step<N, R, 1>()] = v[r];
             }
         }
         __syncthreads();
@@ -372,7 +363,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
             if (bb < NB) {
                 float2 v[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = data[pad(bb + r * NB)];
+                for (int r = 0; r < R; ++r) v[r] = data[read_base<N, R>(bb) + r * read_step<N, R>()];
                 twiddle<LOG2N, R, NS, true>(v, bb, fac);
                 Dft<R, true>::run(v);
 #pragma unroll
@@ -388,9 +379,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
 template <int LOG2N>
 hipError_t fwd(const int16_t* rf, int ntraces, int T, float2* out, bool blocked, int L, int ncol, int kpad,
                hipStream_t st) {
-    // about three record pairs per workgroup, four workgroups per CU
-    const int npairs = (ntraces + 1) / 2;
-    const int blocks = npairs < 1024 ? npairs : (npairs + 2) / 3 < 1024 ? 1024 : (npairs + 2) / 3;
+    const int blocks = (ntraces + 1) / 2;  // one record pair per workgroup
     if (blocked)
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces, T,
                            out, L, ncol, kpad);
