@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--cpu-frames", type=int, default=10, help="oracle frames timed for cpu_baseline (0: skip)")
     ap.add_argument("--no-das", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle check of the timed frame")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the split-precision decomposition report on the large workload")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -85,6 +87,46 @@ def timed(fn, steps, warmup, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps  # ms
+
+
+def precision_report(kk, C, torch, np, args):
+    """Large workload (192 elements, 75 transmits, 4096 samples, Eq. 6 j = 0, 37, M = 9,
+    384 x 768 pixels): the decomposition in FP32 and in the two split-precision forms, each
+    timed and compared with the FP64 oracle (sampled pixels of the beamformed sets) and with the
+    FP32 run (whole image)."""
+    import oracle as O
+    w = C.LARGE
+    ds = C.speckle_dataset(w, seed=3, n_scat=20_000)
+    su = kk.make_setup(w, with_das=False)
+    dev = torch.device("cuda", 0)
+    rf, sh, pd = kk.to_device(ds.rf), kk.to_device(su.luts["shift"]), kk.to_device(su.plan)
+    R64 = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    rng = np.random.default_rng(1)
+    xi, zi = rng.integers(0, w.X, 400), rng.integers(0, w.Z, 400)
+    ref = O.kk_beamform(R64, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    out = {"workload": "large: 192 el, 75 tx in +-18 deg, 4096 samples, Eq.6 j=0,37 M=9 (%d pairs), %dx%d px"
+                       % (len(su.sel["pairs"]), w.X, w.Z)}
+    img32 = None
+    for name, prec in (("fp32", kk.PREC_FP32), ("bf16x3", kk.PREC_BF16X3), ("fp16x3", kk.PREC_FP16X3)):
+        rt = torch.empty((w.N, su.M, w.T), dtype=torch.complex64, device=dev)
+        ws = torch.empty(kk.decompose_workspace_bytes(su.geom, w.N, su.M, su.tpad, prec), dtype=torch.uint8,
+                         device=dev)
+        ms = timed(lambda: kk.decompose(rf, su.geom, sh, su.M, su.tpad, out=rt, ws=ws, precision=prec),
+                   max(5, args.steps // 10), 2, torch)
+        img = kk.beamform(rt, su.plan, pd)
+        torch.cuda.synchronize()
+        got = img.cpu().numpy()
+        if img32 is None:
+            img32 = got
+        out[name] = {
+            "decompose_us": round(ms * 1e3, 2),
+            "rel_l2_rf_theta_vs_fp64": float(np.linalg.norm(rt.cpu().numpy() - R64) / np.linalg.norm(R64)),
+            "rel_l2_image_vs_fp64": float(np.linalg.norm(got[:, xi, zi] - ref) / np.linalg.norm(ref)),
+            "rel_l2_image_vs_fp32": float(np.linalg.norm(got - img32) / np.linalg.norm(img32)),
+        }
+        print("bench: precision %s decompose %.2f us" % (name, ms * 1e3), file=sys.stderr, flush=True)
+    return out
 
 
 def main():
@@ -162,6 +204,9 @@ def main():
                        das_steps, 3, torch)
         res["das_ms"] = ms_das
         print("bench: DAS %.2f us/frame" % (ms_das * 1e3), file=sys.stderr, flush=True)
+
+    if not args.no_precision:
+        res["precision"] = precision_report(kk, C, torch, np, args)
 
     if args.copy_mb > 0:
         src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
@@ -244,6 +289,8 @@ def main():
         },
         "stage_rooflines": stage_roofs,
     }
+    if "precision" in res:
+        out["precision_large"] = res["precision"]
     if "das_ms" in res:
         das_units = w.X * w.Z * w.N * w.L                 # pixel x (transmit, element) gathers
         out["stage_rooflines"]["das"] = {

@@ -77,7 +77,11 @@ typedef enum kk_scheme {
 } kk_scheme;
 
 typedef enum kk_precision {
-    KK_PREC_FP32 = 0            /* FP32 transforms and contraction (the parity path)         */
+    KK_PREC_FP32 = 0,           /* FP32 transforms and contraction (the parity path)         */
+    KK_PREC_BF16X3 = 1,         /* contraction on BF16 MFMA, split hi+lo, 3 products, FP32   */
+                                /* accumulate (terms exact to ~2^-16)                        */
+    KK_PREC_FP16X3 = 2          /* same on FP16 MFMA with an exact power-of-two prescale     */
+                                /* (terms exact to ~2^-22)                                   */
 } kk_precision;
 
 typedef enum kk_compound_mode {
@@ -181,11 +185,15 @@ int32_t kk_beamform_plan(const int32_t* pairs, int32_t P, int32_t S, int32_t N, 
  *   rf_theta[i][o][n] = (1/tpad) sum_{k <= tpad/2} Y[i][o][k] exp(+2 pi i k n / tpad), n < T.
  *   rf        dev in  int16 [N][L][T]
  *   shift_q   dev in  int32 [M][L] (kk_build_luts)
- *   tpad      FFT length from kk_build_luts: power of two, T < tpad <= 8192... see limits
- *   precision KK_PREC_FP32
+ *   tpad      FFT length from kk_build_luts (a power of two)
+ *   precision KK_PREC_FP32 (the parity path), or KK_PREC_BF16X3 / KK_PREC_FP16X3: the
+ *             contraction on 16-bit MFMA with hi+lo split operands (W X ~ Wh Xh + Wh Xl +
+ *             Wl Xh, FP32 accumulate); transforms stay FP32.  Each term is exact to about
+ *             2^-16 (BF16) or 2^-22 (FP16) of its size; FP16 inputs are scaled by an exact
+ *             power of two chosen from T so that no value exceeds 2^15.
  *   rf_theta  dev out complex float [N][M][T]
  *   ws        dev workspace of at least kk_decompose_workspace_bytes() bytes
- * Limits: 1 <= N, 1 <= M, 1 <= L <= 1024, 1 <= T < tpad, tpad in {256, ..., 8192}.
+ * Limits: 1 <= N, 1 <= M, 1 <= L <= 65536, 1 <= T <= tpad, tpad in {256, ..., 8192}.
  * Errors: KK_E_NULL, KK_E_ARG, KK_E_WORKSPACE, KK_E_UNSUPPORTED (precision), KK_E_HIP.
  * ------------------------------------------------------------------------------------- */
 size_t kk_decompose_workspace_bytes(const kk_geom* g, int32_t N, int32_t M, int32_t tpad,

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "../../include/kk.h"
 #include "kk_internal.h"
 #include "kk_plan.h"
@@ -232,6 +234,198 @@ __global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Split-precision contraction: the same per-bin product with 16-bit MFMA inputs.  Every
+// spectrum value and phase is split as x = hi + lo, hi = round16(x), lo = round16(x - hi)
+// (BF16 or FP16), and Y = Wh Xh + Wh Xl + Wl Xh accumulated in FP32 on
+// v_mfma_f32_32x32x16_{bf16,f16} (eight complex elements per instruction: K = {Re, Im} x 8).
+// The dropped Wl Xl term and the residuals are below 2^-16 (BF16) or 2^-22 (FP16) of the
+// terms.  FP16 spectra are first scaled by 2^e so that |X| < 2^15 (|X| <= 2 T 32768 for int16
+// records), and Y by 2^-e (both exact).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kXsWords = kBinBlock * 2 * kChunkL + 4;  // per column: [bin][hi, lo][l] + pad (16 B)
+constexpr int kWsBlock = 2 * kChunkL + 4;              // per (bin, angle, row type): [hi, lo][l] + pad
+
+template <bool F16>
+__device__ __forceinline__ uint32_t half_bits(float x) {
+    if constexpr (F16)
+        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+    else
+        return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x);
+}
+template <bool F16>
+__device__ __forceinline__ float half_value(float x) {
+    if constexpr (F16)
+        return (float)(_Float16)x;
+    else
+        return (float)(__bf16)x;
+}
+// (re, im) -> hi pair and lo pair, low half = re
+template <bool F16>
+__device__ __forceinline__ void split_pair(float re, float im, uint32_t& hi, uint32_t& lo) {
+    const float rh = half_value<F16>(re), ih = half_value<F16>(im);
+    hi = half_bits<F16>(re) | (half_bits<F16>(im) << 16);
+    lo = half_bits<F16>(re - rh) | (half_bits<F16>(im - ih) << 16);
+}
+
+template <int LOG2N, bool F16>
+__device__ __forceinline__ void split_store(const ContractStage& st, uint32_t* xs, uint32_t* ws, const float2* fac,
+                                            int kb, int l0, int L, int M, int rt, int tid, float xscale) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int f = tid + u * kContractThreads;
+        const int i = f >> 6, j = f & 63;        // column, float4 (two bins of one element)
+        const int l = j >> 2, q = j & 3;
+        const bool in = l0 + l < L;
+        const float v[4] = {st.v[u].x * xscale, st.v[u].y * xscale, st.v[u].z * xscale, st.v[u].w * xscale};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t hi, lo;
+            split_pair<F16>(v[2 * h], v[2 * h + 1], hi, lo);
+            uint32_t* d = xs + i * kXsWords + ((2 * q + h) * 2) * kChunkL + l;
+            d[0] = in ? hi : 0u;
+            d[kChunkL] = in ? lo : 0u;
+        }
+    }
+    if (tid < 256) {  // waves 0..3: phases of (angle, element) for the block's 8 bins
+        const int ol = tid & 15, ll = tid >> 4;
+        const bool valid = rt * 16 + ol < M && l0 + ll < L;
+        const float2 w0 = shear_phase<LOG2N>((uint32_t)(kb * kBinBlock), st.s, fac);
+        const float2 d1 = shear_phase<LOG2N>(1u, st.s, fac);
+        const float2 d2 = cmul2(d1, d1), d4 = cmul2(d2, d2);
+        const float2 w1 = cmul2(w0, d1), w2 = cmul2(w0, d2), w3 = cmul2(w1, d2);
+        const float2 w[8] = {w0, w1, w2, w3, cmul2(w0, d4), cmul2(w1, d4), cmul2(w2, d4), cmul2(w3, d4)};
+#pragma unroll
+        for (int b = 0; b < kBinBlock; ++b) {
+            uint32_t rh, rl, ih, il;
+            split_pair<F16>(w[b].x, -w[b].y, rh, rl);  // Re rows: (Wr, -Wi)
+            split_pair<F16>(w[b].y, w[b].x, ih, il);   // Im rows: (Wi, Wr)
+            uint32_t* dr = ws + ((b * 16 + ol) * 2 + 0) * kWsBlock + ll;
+            uint32_t* di = ws + ((b * 16 + ol) * 2 + 1) * kWsBlock + ll;
+            dr[0] = valid ? rh : 0u;
+            dr[kChunkL] = valid ? rl : 0u;
+            di[0] = valid ? ih : 0u;
+            di[kChunkL] = valid ? il : 0u;
+        }
+    }
+}
+
+// MFMA operands of one chunk: two K-steps of 8 elements, hi and lo of A (phases) and B (spectrum)
+struct SplitOperands {
+    u32x4 ah[2], al[2], bh[2], bl[2];
+};
+
+__device__ __forceinline__ void split_read(SplitOperands& op, const uint32_t* xs, const uint32_t* ws, int col, int g,
+                                           int wave) {
+    // B lane (g, col): elements 4g..4g+3 of K-step s for transmit col; A lane (g, row col):
+    // the same elements for row (angle col % 16, Re/Im col / 16)
+    const uint32_t* xb = xs + col * kXsWords + wave * 2 * kChunkL + 4 * g;
+    const uint32_t* wa = ws + ((wave * 16 + (col & 15)) * 2 + (col >> 4)) * kWsBlock + 4 * g;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        op.bh[s] = *reinterpret_cast<const u32x4*>(xb + 8 * s);
+        op.bl[s] = *reinterpret_cast<const u32x4*>(xb + kChunkL + 8 * s);
+        op.ah[s] = *reinterpret_cast<const u32x4*>(wa + 8 * s);
+        op.al[s] = *reinterpret_cast<const u32x4*>(wa + kChunkL + 8 * s);
+    }
+}
+
+template <bool F16>
+__device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                      0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+}
+
+template <bool F16>
+__device__ __forceinline__ void split_mfma(floatx16 (&acc)[2], const SplitOperands& op) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        acc[s] = mfma16<F16>(op.ah[s], op.bl[s], acc[s]);
+        acc[s] = mfma16<F16>(op.al[s], op.bh[s], acc[s]);
+        acc[s] = mfma16<F16>(op.ah[s], op.bh[s], acc[s]);
+    }
+}
+
+// Same workgroup shape and software pipeline as contract_kernel.
+template <int LOG2N, bool F16>
+__global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
+    const float2* __restrict__ X, const int32_t* __restrict__ shift, float2* __restrict__ Y, int ntx, int M, int L,
+    int ncol, int kpad, float xscale, float yscale) {
+    constexpr int N = 1 << LOG2N;
+    __shared__ float2 fac[64 + N / 64];
+    __shared__ __attribute__((aligned(16))) uint32_t xs[2][32 * kXsWords];
+    __shared__ __attribute__((aligned(16))) uint32_t ws[2][kBinBlock * 16 * 2 * kWsBlock];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int kb = blockIdx.x, rt = blockIdx.y, ct = blockIdx.z;
+    build_phase_factors<LOG2N>(fac, tid);
+    const int g = lane >> 5, col = lane & 31;
+
+    floatx16 acc[2];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[0][v] = acc[1][v] = 0.0f;
+
+    const int nchunks = (L + kChunkL * kStages - 1) / (kChunkL * kStages) * kStages;
+    ContractStage st[kStages];
+    SplitOperands op[2];
+#pragma unroll
+    for (int u = 0; u < kStages; ++u) contract_load(st[u], X, shift, kb, ncol, ct, L, u * kChunkL, M, rt, tid);
+    __syncthreads();  // phase factors complete
+    split_store<LOG2N, F16>(st[0], xs[0], ws[0], fac, kb, 0, L, M, rt, tid, xscale);
+    contract_load(st[0], X, shift, kb, ncol, ct, L, kStages * kChunkL, M, rt, tid);
+    split_store<LOG2N, F16>(st[1], xs[1], ws[1], fac, kb, kChunkL, L, M, rt, tid, xscale);
+    contract_load(st[1], X, shift, kb, ncol, ct, L, (kStages + 1) * kChunkL, M, rt, tid);
+    __syncthreads();
+    split_read(op[0], xs[0], ws[0], col, g, wave);
+    __syncthreads();  // every wave has chunk 0's operands before buffer 0 takes chunk 2
+    for (int c0 = 0; c0 < nchunks; c0 += kStages) {
+#pragma unroll
+        for (int u = 0; u < kStages; ++u) {
+            const int c = c0 + u;
+            split_mfma<F16>(acc, op[u & 1]);
+            split_read(op[(u + 1) & 1], xs[(u + 1) & 1], ws[(u + 1) & 1], col, g, wave);
+            const int s2 = (u + 2) % kStages;
+            split_store<LOG2N, F16>(st[s2], xs[u & 1], ws[u & 1], fac, kb, (c + 2) * kChunkL, L, M, rt, tid, xscale);
+            contract_load(st[s2], X, shift, kb, ncol, ct, L, (c + 2 + kStages) * kChunkL, M, rt, tid);
+            __syncthreads();
+        }
+    }
+    constexpr int kYCol = 16 * kBinBlock + 1;
+    static_assert(32 * kYCol * 8 <= (int)sizeof(xs), "result staging fits the spectrum buffers");
+    float2* yst = reinterpret_cast<float2*>(&xs[0][0]);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        yst[col * kYCol + ol * kBinBlock + wave] =
+            make_float2((acc[0][v] + acc[1][v]) * yscale, (acc[0][v + 8] + acc[1][v + 8]) * yscale);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int f = tid + u * kContractThreads;
+        const int run = f >> 3, q = f & 7;
+        const int il = run >> 4, ol = run & 15;
+        const int i = ct * 32 + il, o = rt * 16 + ol;
+        if (i < ntx && o < M) Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q] = yst[il * kYCol + ol * kBinBlock + q];
+    }
+}
+
+template <int LOG2N, bool F16>
+hipError_t contract_split(const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L, int ncol, int kpad,
+                          float xscale, hipStream_t st) {
+    const dim3 grid((1 << LOG2N) / 2 / kBinBlock, (M + 15) / 16, ncol / 32);
+    hipLaunchKernelGGL((contract_split_kernel<LOG2N, F16>), grid, dim3(kContractThreads), 0, st, X, shift, Y, ntx, M,
+                       L, ncol, kpad, xscale, 1.0f / xscale);
+    return hipGetLastError();
+}
+
 template <int LOG2N>
 hipError_t contract(const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L, int ncol, int kpad,
                     hipStream_t st) {
@@ -240,6 +434,20 @@ hipError_t contract(const float2* X, const int32_t* shift, float2* Y, int ntx, i
     hipLaunchKernelGGL((contract_kernel<LOG2N>), grid, dim3(kContractThreads), 0, st, X, shift, Y, ntx, M, L, ncol,
                        kpad);
     return hipGetLastError();
+}
+
+template <bool F16>
+hipError_t launch_contract_split(int log2n, const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L,
+                                 int ncol, int kpad, float xscale, hipStream_t st) {
+    switch (log2n) {
+        case 8: return contract_split<8, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 9: return contract_split<9, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 10: return contract_split<10, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 11: return contract_split<11, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 12: return contract_split<12, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 13: return contract_split<13, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_contract(int log2n, const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L,
@@ -301,7 +509,9 @@ extern "C" {
 
 size_t kk_decompose_workspace_bytes(const kk_geom* g, int32_t N, int32_t M, int32_t tpad, int32_t precision) {
     kk::DecomposeLayout d;
-    if (!g || precision != KK_PREC_FP32 || !kk::decompose_layout(g, N, M, tpad, &d)) return 0;
+    if (!g || (precision != KK_PREC_FP32 && precision != KK_PREC_BF16X3 && precision != KK_PREC_FP16X3) ||
+        !kk::decompose_layout(g, N, M, tpad, &d))
+        return 0;
     return d.total;
 }
 
@@ -309,7 +519,8 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
                      int32_t precision, float* rf_theta, void* ws, size_t ws_bytes, void* stream) {
     using namespace kk;
     if (!rf || !g || !shift_q || !rf_theta || !ws) return KK_E_NULL;
-    if (precision != KK_PREC_FP32) return KK_E_UNSUPPORTED;
+    if (precision != KK_PREC_FP32 && precision != KK_PREC_BF16X3 && precision != KK_PREC_FP16X3)
+        return KK_E_UNSUPPORTED;
     if (N < 1 || M < 1 || g->L < 1 || g->L > 65536 || g->T < 1) return KK_E_ARG;
     DecomposeLayout d;
     if (!decompose_layout(g, N, M, tpad, &d)) return KK_E_ARG;
@@ -321,7 +532,18 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
     float2* Y = reinterpret_cast<float2*>(w + d.y_off);
     if (launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st) != hipSuccess)
         return KK_E_HIP;
-    if (launch_contract(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, st) != hipSuccess) return KK_E_HIP;
+    hipError_t ce;
+    if (precision == KK_PREC_FP32) {
+        ce = launch_contract(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, st);
+    } else if (precision == KK_PREC_BF16X3) {
+        ce = launch_contract_split<false>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
+    } else {
+        // |X| <= 2 T 32768 (analytic mask x int16 record): scale by 2^e so that it stays below 2^15
+        int e = 15;
+        for (int64_t bound = 2 * (int64_t)g->T * 32768; bound > 1; bound = (bound + 1) / 2) --e;
+        ce = launch_contract_split<true>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, std::ldexp(1.0f, e), st);
+    }
+    if (ce != hipSuccess) return KK_E_HIP;
     NyquistSum nyq{X, shift_q, M, g->L, d.ncol};
     if (launch_fft_inverse(Y, N * M, d.kpad, d.log2n, reinterpret_cast<float2*>(rf_theta), g->T, st, &nyq) !=
         hipSuccess)

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libkk.so")
 KK_OK, KK_E_NULL, KK_E_ARG, KK_E_CAPACITY, KK_E_WORKSPACE, KK_E_RANGE, KK_E_HIP, KK_E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
 SCHEME_SHIFTED, SCHEME_CONFOCAL, SCHEME_SAME, SCHEME_FULL_UNIFORM = 0, 1, 2, 3
-PREC_FP32 = 0
+PREC_FP32, PREC_BF16X3, PREC_FP16X3 = 0, 1, 2
 COMPOUND_COHERENT, COMPOUND_INCOHERENT = 0, 1
 
 EXPORTS = [

@@ -178,7 +178,7 @@ def test_decompose_errors(kk):
     rf = torch.zeros((w.N, w.L, w.T), dtype=torch.int16, device="cuda")
     sh = kk.to_device(su.luts["shift"])
     with pytest.raises(kk.KKError) as e:
-        kk.decompose(rf, su.geom, sh, su.M, su.tpad, precision=1)
+        kk.decompose(rf, su.geom, sh, su.M, su.tpad, precision=9)   # not a kk_precision
     assert e.value.status == kk.KK_E_UNSUPPORTED
     with pytest.raises(kk.KKError) as e:
         kk.decompose(rf, su.geom, sh, su.M, 3000)
