@@ -256,6 +256,153 @@ int32_t das_beamform(const int16_t* rf, int32_t N, const kk_geom* g,
                      const void* plan_host, const void* plan_dev, size_t plan_bytes,
                      float* image, void* ws, size_t ws_bytes, void* stream);
 
+/* =======================================================================================
+ * Frame ensembles: many KK frames of uneven shapes (element counts, transmit and receive
+ * angle sets, record lengths, grids) imaged as one unit of work.
+ *
+ * Every frame goes through the steps of kk_decompose and kk_beamform (Eq. 3, Eq. 5, and
+ * Eq. 8 / Eq. 9 when an intensity is asked for), but each step runs as one launch over all
+ * frames of a shape class instead of one launch per frame: the forward transforms,
+ * contractions and inverse transforms per FFT length, and the delay-gather as one persistent
+ * work-queue launch per window class over every (frame, set, pair share, pixel tile) unit.
+ * Results equal the per-frame entry points' for the same precision and pair split.
+ *
+ * Buffers: the channel data of all frames is one packed int16 array, the images one packed
+ * complex array and the intensities one packed float array; kk_ensemble_frame_query gives
+ * each frame's offsets.  The workspace holds RF_theta of every frame (all at once), the pair
+ * shares of split frames, the queue counters, and the spectra of one decomposition group:
+ * frames are decomposed in groups whose spectra fit the budget given to kk_ensemble_plan.
+ * ===================================================================================== */
+
+typedef struct kk_ensemble_frame {
+    kk_geom geom;              /* this frame's acquisition (L, T, pitch, c, fs, t0)            */
+    int32_t N;                 /* transmit angles                                              */
+    int32_t M;                 /* distinct receive angles                                      */
+    int32_t tpad;              /* FFT length (kk_build_luts)                                   */
+    int32_t mode;              /* intensity: KK_COMPOUND_COHERENT or _INCOHERENT, -1 for none  */
+    const int32_t* shift_q;    /* host [M][L] shear table (kk_build_luts)                      */
+    const void* plan;          /* host kk_beamform_plan buffer for this (N, M, T) and grid     */
+    size_t plan_bytes;
+} kk_ensemble_frame;
+
+#define KK_ENSEMBLE_CLASSES 8  /* window classes: 64, 128, ..., 512 record samples per tile */
+
+/* Launch-shape choices of an ensemble (what kk_ensemble_autotune searches). */
+typedef struct kk_ensemble_tuning {
+    int32_t pair_tile[KK_ENSEMBLE_CLASSES]; /* per window class: pairs per gather work unit
+                                               (a set is split into ceil(set / pair_tile)
+                                               shares, at most 8); 0 = whole sets        */
+    int32_t queue;             /* 0: one work list, units in descending cost order;
+                                  1: one list per XCD, frames in order, equal cost per list,
+                                     drained lists take the others' remaining units      */
+    int32_t reserved[7];       /* zero                                                   */
+} kk_ensemble_tuning;
+
+typedef struct kk_ensemble_frame_info {
+    int64_t rf_offset;         /* int16 elements into the packed channel data: [N][L][T]       */
+    int64_t image_offset;      /* complex elements into the packed images: [S][X][Z]           */
+    int64_t intensity_offset;  /* float elements into the packed intensities: [X][Z]; -1: none */
+    int64_t rf_theta_offset;   /* complex elements into the workspace: RF_theta [N][M][T]      */
+    int64_t share_offset;      /* complex elements into the workspace: shares [K][S][X][Z], -1 */
+    int32_t N, L, T, M, S, X, Z, P, tpad;
+    int32_t cap;               /* window class (record samples per pair and tile)              */
+    int32_t split;             /* pair shares per set (K)                                      */
+    int32_t group;             /* decomposition group                                          */
+    int32_t mode;
+    int32_t plan_offset;       /* int32 words into the ensemble plan: this frame's plan copy    */
+    int32_t shift_offset;      /* int32 words into the ensemble plan: its shear table          */
+    int32_t reserved;
+} kk_ensemble_frame_info;
+
+typedef struct kk_ensemble_sizes {
+    int64_t rf_elems;          /* packed channel data length (int16 elements)                  */
+    int64_t image_elems;       /* packed images length (complex elements)                      */
+    int64_t intensity_elems;   /* packed intensities length (float elements)                   */
+    int64_t ws_bytes;          /* workspace                                                    */
+    int64_t units_offset;      /* workspace byte offset of the per-workgroup unit counts:
+                                  int32 [KK_ENSEMBLE_CLASSES][1024], row = window class index  */
+    int32_t nframes, ngroups, nlaunches, nunits;  /* frames, decomposition groups, kernel
+                                  launches of a full run, gather work units                    */
+    int32_t precision;
+    int32_t reserved[3];
+} kk_ensemble_sizes;
+
+/* Stages of kk_ensemble_run (bit mask). */
+enum {
+    KK_STAGE_FFT = 1,          /* analytic spectra                                             */
+    KK_STAGE_CONTRACT = 2,     /* Eq. 3 per-bin contraction                                    */
+    KK_STAGE_INVERSE = 4,      /* inverse transforms -> RF_theta                               */
+    KK_STAGE_GATHER = 8,       /* Eq. 5 delay-gather                                           */
+    KK_STAGE_REDUCE = 16,      /* pair-share sums and Eq. 8 / 9 intensities                    */
+    KK_STAGE_ALL = 31
+};
+
+/* kk_ensemble_default_tuning (host): whole sets, per-XCD lists. */
+void kk_ensemble_default_tuning(kk_ensemble_tuning* tuning);
+
+/* kk_ensemble_plan (host) - the ensemble plan: frame offsets, the copied per-frame plans and
+ * shear tables, the work tables of every grouped launch and the gather work lists.  Opaque
+ * bytes; copy to device memory unchanged.
+ *   frames, nframes   frame descriptions (nframes >= 1); their plans must be KK plans
+ *   precision         KK_PREC_* for every contraction of the ensemble
+ *   tuning            launch shapes (NULL: kk_ensemble_default_tuning)
+ *   spectra_budget    bytes of workspace the decomposition spectra of one group may use;
+ *                     0 = all frames in one group.  A frame larger than the budget forms a
+ *                     group of its own.
+ *   plan, plan_bytes  host out; *plan_bytes_out = required size (always written)
+ * Errors: KK_E_NULL, KK_E_ARG (a frame's sizes, mode or plan disagree), KK_E_WORKSPACE (a
+ * frame's plan is not a valid KK plan), KK_E_UNSUPPORTED (precision), KK_E_CAPACITY (plan
+ * too small; plan = NULL with plan_bytes = 0 queries the size). */
+int32_t kk_ensemble_plan(const kk_ensemble_frame* frames, int32_t nframes, int32_t precision,
+                         const kk_ensemble_tuning* tuning, int64_t spectra_budget,
+                         void* plan, size_t plan_bytes, size_t* plan_bytes_out);
+
+/* kk_ensemble_query / kk_ensemble_frame_query (host) - sizes of the packed buffers and the
+ * workspace, and frame f's offsets and shapes.  Errors: KK_E_NULL, KK_E_WORKSPACE (not an
+ * ensemble plan), KK_E_ARG (f out of range). */
+int32_t kk_ensemble_query(const void* plan_host, size_t plan_bytes, kk_ensemble_sizes* sizes);
+int32_t kk_ensemble_frame_query(const void* plan_host, size_t plan_bytes, int32_t f,
+                                kk_ensemble_frame_info* info);
+
+/* kk_ensemble_run (device) - enqueue the selected stages of the whole ensemble on stream
+ * (KK_STAGE_ALL for a complete run; a stage reads what the previous stages last wrote).
+ *   plan_host, plan_dev  host and device copies of a kk_ensemble_plan buffer
+ *   rf          dev in  packed int16 channel data
+ *   image       dev out packed complex images
+ *   intensity   dev out packed intensities (NULL allowed when no frame asks for one)
+ *   ws          dev workspace of kk_ensemble_sizes.ws_bytes bytes
+ * The launch list is fixed by the plan, so the same call can be captured into a graph.
+ * Errors: KK_E_NULL, KK_E_WORKSPACE (plan or workspace), KK_E_ARG (stages), KK_E_HIP. */
+int32_t kk_ensemble_run(const void* plan_host, const void* plan_dev, size_t plan_bytes,
+                        const int16_t* rf, float* image, float* intensity, void* ws,
+                        size_t ws_bytes, int32_t stages, void* stream);
+
+/* kk_ensemble_graph_create (host) - capture a complete kk_ensemble_run with these buffers on
+ * `stream` (a created stream, not NULL) into an executable HIP graph; *graph_out receives an
+ * opaque handle owned by the caller until kk_ensemble_graph_destroy.  The graph keeps the
+ * device addresses: the buffers must stay allocated while it is used.
+ * kk_ensemble_graph_launch enqueues one replay on `stream`.
+ * Errors: KK_E_NULL, KK_E_ARG (NULL stream), the errors of kk_ensemble_run, KK_E_HIP. */
+int32_t kk_ensemble_graph_create(const void* plan_host, const void* plan_dev, size_t plan_bytes,
+                                 const int16_t* rf, float* image, float* intensity, void* ws,
+                                 size_t ws_bytes, void* stream, void** graph_out);
+int32_t kk_ensemble_graph_launch(void* graph, void* stream);
+int32_t kk_ensemble_graph_destroy(void* graph);
+
+/* kk_ensemble_autotune (host, synchronous) - measure launch shapes on the device and return
+ * the fastest: the gather queue layout, then per window class present the pair tile (from
+ * whole sets down to 32 pairs), each timed as the median of `reps` gather + reduce runs on
+ * the caller's data after one full run.  Candidates whose plan or workspace exceeds
+ * plan_dev_bytes / ws_bytes are skipped.  *tuning is the starting point and receives the
+ * result; *best_us (may be NULL) the gather + reduce time of the result.
+ * plan_dev (plan_dev_bytes) is device scratch for the candidate plans; it holds the last
+ * candidate's plan on return.  Errors: as kk_ensemble_plan and kk_ensemble_run. */
+int32_t kk_ensemble_autotune(const kk_ensemble_frame* frames, int32_t nframes, int32_t precision,
+                             int64_t spectra_budget, void* plan_dev, size_t plan_dev_bytes,
+                             const int16_t* rf, float* image, float* intensity, void* ws,
+                             size_t ws_bytes, int32_t reps, void* stream,
+                             kk_ensemble_tuning* tuning, float* best_us);
+
 /* Human-readable name of a kk_status value (static string, never NULL). */
 const char* kk_status_string(int32_t status);
 

@@ -14,11 +14,17 @@ to the sizes below.  Every phantom is drawn from a seeded PCG64 generator.
   full      same data, 128 uniform receive angles over +-16 deg, all 3968 pairs.
   large     192 elements, 4096 samples, 75 transmits in +-18 deg; Eq. 6 sets j = 0, 37
             with M = 9 (1350 pair slots, 10.7x); 384 x 768 pixels.
+  ensemble  frames of uneven shapes (ensemble_workloads): each draws 64-192 elements,
+            15-75 transmits, J = 1-3 Eq. 6 sets with odd M giving 4-16x compression, and a
+            grid from 128 x 256 to 384 x 768 pixels with a record long enough for its depth;
+            all frames image one moving speckle medium (ensemble_dataset).
 """
 from __future__ import annotations
 
 import math
 from dataclasses import dataclass
+
+import numpy as np
 
 from .phantom import Acquisition, Dataset, make_dataset, seeded_points, speckle_phantom
 
@@ -111,3 +117,74 @@ def speckle_dataset(w: Workload, seed: int = 2, n_scat: int = 100_000) -> Datase
     sc = speckle_phantom(seed, n_scat, (-half_ap, half_ap), (1e-3, depth - 0.8e-3),
                          points=pts, cysts=[(0.0, zc, 2e-3)])
     return make_dataset(w.acquisition(), sc, meta=dict(workload=w.name, seed=seed, n_scat=n_scat))
+
+
+# ----------------------------------------------------------------------------- ensembles
+
+ENSEMBLE_PITCH = 0.3e-3
+ENSEMBLE_C = 1540.0
+ENSEMBLE_FS = 20e6
+ENSEMBLE_FC = 5e6
+
+
+def ensemble_workloads(n_frames: int = 200, seed: int = 4000, L_range=(64, 192), N_range=(15, 75),
+                       scale_range=(1.0, 3.0), compression=(4.0, 16.0)) -> list:
+    """Seeded frame shapes of a batched ensemble.  Per frame: L and N uniform integers; the
+    transmit half range uniform in 10-18 deg; J uniform in 1..3 Eq. 6 sets with j spread over
+    0..floor(N/2); M odd with L / (J M) inside the compression range; a grid of 128 s lateral x
+    256 s axial pixels at lambda/2 (s uniform in scale_range), x centred, from z = 0; T covers
+    the grid depth (4 samples per axial pixel at fs = 4 fc) plus 128 samples, rounded up to 64."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(n_frames):
+        L = int(rng.integers(L_range[0], L_range[1] + 1))
+        N = int(rng.integers(N_range[0], N_range[1] + 1))
+        th = float(rng.uniform(10.0, 18.0))
+        J = int(rng.integers(1, 4))
+        lo, hi = L / (compression[1] * J), L / (compression[0] * J)
+        Ms = [m for m in range(1, 4 * L, 2) if lo <= m <= hi]
+        if not Ms:
+            Ms = [max(1, int(round(hi)) | 1)]
+        M = int(Ms[int(rng.integers(0, len(Ms)))])
+        half = N // 2
+        j_list = tuple(sorted({(k * half) // (J - 1) for k in range(J)})) if J > 1 else (0,)
+        s = float(rng.uniform(scale_range[0], scale_range[1]))
+        X = max(16, int(round(128 * s)))
+        Z = max(16, int(round(256 * s)))
+        T = (4 * Z + 128 + 63) // 64 * 64
+        out.append(Workload("ensemble%d" % f, L=L, T=T, N=N, pitch=ENSEMBLE_PITCH, c=ENSEMBLE_C, fs=ENSEMBLE_FS,
+                            fc=ENSEMBLE_FC, theta_max_deg=th, scheme=SCHEME_SHIFTED, M=M, j_list=j_list, X=X, Z=Z,
+                            z0=0.0))
+    return out
+
+
+def ensemble_medium(workloads, seed: int = 4001, per_lambda2: float = 0.5, max_step: float = 50e-6):
+    """One speckle medium covering every frame's field: uniform positions, N(0,1) amplitudes,
+    per_lambda2 scatterers per lambda^2, and a velocity per scatterer of uniform direction and
+    speed uniform in [0, max_step] per frame.  Returns (x, z, a, vx, vz)."""
+    lam = ENSEMBLE_C / ENSEMBLE_FC
+    half = max(max((w.L - 1) * w.pitch / 2.0 + w.pitch / 2.0, (w.X - 1) * w.dx / 2.0) for w in workloads)
+    depth = max(w.T * w.c / (2.0 * w.fs) for w in workloads)
+    area = 2 * half * depth
+    n = max(1, int(round(per_lambda2 * area / (lam * lam))))
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-half, half, n)
+    z = rng.uniform(1e-3, depth, n)
+    a = rng.standard_normal(n)
+    sp = rng.uniform(0.0, max_step, n)
+    ang = rng.uniform(0.0, 2 * math.pi, n)
+    return x, z, a, sp * np.cos(ang), sp * np.sin(ang)
+
+
+def ensemble_dataset(w: Workload, medium, frame: int) -> Dataset:
+    """Channel data of frame `frame` of the ensemble: the medium moved by `frame` steps, the
+    scatterers inside this frame's field (its aperture or grid, whichever is wider, plus 5 mm,
+    and its record depth)."""
+    from .phantom import Scatterers
+    x, z, a, vx, vz = medium
+    xf, zf = x + frame * vx, z + frame * vz
+    half = max((w.L - 1) * w.pitch / 2.0 + w.pitch / 2.0, (w.X - 1) * w.dx / 2.0) + 5e-3
+    depth = w.T * w.c / (2.0 * w.fs)
+    keep = (np.abs(xf) <= half) & (zf > 0) & (zf <= depth)
+    sc = Scatterers(xf[keep].copy(), zf[keep].copy(), a[keep].copy())
+    return make_dataset(w.acquisition(), sc, meta=dict(workload=w.name, frame=frame))

@@ -238,12 +238,12 @@ __device__ __forceinline__ void gather_pair(float2 (&acc)[kRows], const PairDela
     gather_rows<0, DAS, DEPTH>(acc, d, c, s0, s1, win);
 }
 
+// One work unit (set, pair share, tile) of one plan; unit < 0 takes blockIdx.x through the
+// XCD-contiguous remap.  lds: at least Lds<CAP>::kBytes.
 template <int CAP, bool DAS>
-__global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restrict__ rec,
-                                                          const int32_t* __restrict__ plan,
-                                                          float2* __restrict__ out, int n_arg, int m_arg,
-                                                          int t_arg) {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[Lds<CAP>::kBytes];
+__device__ __forceinline__ void gather_body(const float2* __restrict__ rec, const int32_t* __restrict__ plan,
+                                            float2* __restrict__ out, int n_arg, int m_arg, int t_arg, int unit,
+                                            unsigned char* lds) {
     // a device plan that does not describe this call is ignored (uniform early exit)
     if (plan[PW_MAGIC] != kPlanMagic || plan[PW_KIND] != (DAS ? kPlanKindDAS : kPlanKindKK) ||
         plan[PW_N] != n_arg || plan[PW_M] != m_arg || plan[PW_T] != t_arg || plan[PW_CAP] != CAP ||
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restri
     const int off_set = plan[PW_OFF_SET];
     const int ntiles = nxt * nzt;
     // work unit r = (set, pair share, tile)
-    const int r = xcd_remap(blockIdx.x, ntiles * S * K);
+    const int r = unit >= 0 ? unit : xcd_remap(blockIdx.x, ntiles * S * K);
     const int sh = r / ntiles;
     const int s = sh / K, h = sh - s * K;
     pv.tile = r - sh * ntiles;
@@ -350,11 +350,74 @@ __global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restri
     if (x < X && z < Z) out[(((size_t)h * S + s) * X + x) * Z + z] = v;
 }
 
+template <int CAP, bool DAS>
+__global__ __launch_bounds__(kThreads) void gather_kernel(const float2* __restrict__ rec,
+                                                          const int32_t* __restrict__ plan,
+                                                          float2* __restrict__ out, int n_arg, int m_arg,
+                                                          int t_arg) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[Lds<CAP>::kBytes];
+    gather_body<CAP, DAS>(rec, plan, out, n_arg, m_arg, t_arg, -1, lds);
+}
+
+// Persistent gather over the work units of one window class of a frame ensemble.  The units
+// sit in kQueueLists lists; workgroup b starts on list b mod kQueueLists (the XCD the hardware
+// places it on when workgroups are dealt to the XCDs in turn) and takes units from its front
+// with an atomic counter; once that list is drained it moves on to the next lists, taking
+// their remaining units.  Every workgroup stops after one pass over all lists, so the launch
+// ends when every list is drained.  A unit's results are written by exactly the workgroup
+// that took it, so the images do not depend on the order.  (One class per kernel: a kernel
+// holding several classes' bodies needs more registers than any one of them.)
+template <int CAP>
+__global__ __launch_bounds__(kThreads) void gather_queue_kernel(const GatherEntry* __restrict__ tab,
+                                                                const int2* __restrict__ items,
+                                                                const int32_t* __restrict__ list_begin,
+                                                                int32_t* __restrict__ counters,
+                                                                const float2* __restrict__ rec,
+                                                                const int32_t* __restrict__ plan,
+                                                                float2* __restrict__ image, float2* __restrict__ part,
+                                                                int32_t* __restrict__ wg_units) {
+    __shared__ __attribute__((aligned(16))) unsigned char lds[Lds<CAP>::kBytes];
+    __shared__ int next_item;
+    int list = 0;   // lists passed so far (thread 0)
+    int taken = 0;  // units this workgroup took (thread 0)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int got = -1;
+            while (list < kQueueLists) {
+                const int q = ((int)blockIdx.x + list) % kQueueLists;
+                const int i = atomicAdd(&counters[q], 1);
+                if (i < list_begin[q + 1] - list_begin[q]) {
+                    got = list_begin[q] + i;
+                    ++taken;
+                    break;
+                }
+                ++list;
+            }
+            next_item = got;
+        }
+        __syncthreads();  // also orders the previous unit's LDS reads before this unit's writes
+        const int it = next_item;
+        if (it < 0) break;
+        const int2 w = items[it];
+        const GatherEntry e = tab[w.x];
+        if (e.cap == CAP)
+            gather_body<CAP, false>(rec + e.rec_off, plan + e.plan_off, (e.split > 1 ? part : image) + e.out_off, e.n,
+                                    e.m, e.t, w.y, lds);
+        __syncthreads();  // every thread has read next_item and the unit's LDS before they are reused
+    }
+    // per-workgroup unit counts: their sum equals the number of units when each was taken once
+    if (wg_units && threadIdx.x == 0) wg_units[blockIdx.x] = taken;
+}
+
+__global__ void fill_zero_kernel(int32_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 // Sum of the K pair shares of each set (fixed order), written as the per-set images, and the
 // Eq. 8 / Eq. 9 intensity of the set images when requested.
-__global__ void reduce_kernel(const float2* __restrict__ part, int K, int S, int npix, float2* __restrict__ image,
-                              float* __restrict__ inten, int mode) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reduce_body(const float2* __restrict__ part, int K, int S, int npix,
+                                            float2* __restrict__ image, float* __restrict__ inten, int mode, int i) {
     if (i >= npix) return;
     float2 coh = make_float2(0.f, 0.f);
     float inc = 0.f;
@@ -371,6 +434,23 @@ __global__ void reduce_kernel(const float2* __restrict__ part, int K, int S, int
         inc += v.x * v.x + v.y * v.y;
     }
     if (inten) inten[i] = (mode == KK_COMPOUND_COHERENT) ? coh.x * coh.x + coh.y * coh.y : inc;
+}
+
+__global__ void reduce_kernel(const float2* __restrict__ part, int K, int S, int npix, float2* __restrict__ image,
+                              float* __restrict__ inten, int mode) {
+    reduce_body(part, K, S, npix, image, inten, mode, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Grouped share reduction and compounding: block b covers pixels (b - block0) * 256 .. of
+// frame entry blk[b].  The shares sit in the workspace when the frame's plan splits its pairs;
+// otherwise the images themselves are the single share (read only, not rewritten).
+__global__ __launch_bounds__(256) void reduce_grouped(const ReduceEntry* __restrict__ tab,
+                                                     const int32_t* __restrict__ blk, const float2* part,
+                                                     float2* image, float* __restrict__ inten) {
+    const ReduceEntry e = tab[blk[blockIdx.x]];
+    const int i = ((int)blockIdx.x - e.block0) * 256 + (int)threadIdx.x;
+    reduce_body(e.K > 1 ? part + e.part_off : image + e.img_off, e.K, e.S, e.npix,
+                e.K > 1 ? image + e.img_off : nullptr, e.inten_off >= 0 ? inten + e.inten_off : nullptr, e.mode, i);
 }
 
 template <int CAP, bool DAS>
@@ -399,6 +479,41 @@ hipError_t dispatch_gather(const float2* rec, const int32_t* h, const int32_t* p
 }
 
 }  // namespace
+
+hipError_t launch_fill_zero(int32_t* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_queue(int cap, const GatherEntry* tab, const int2* items, const int32_t* list_begin,
+                               int32_t* counters, int workgroups, const float2* rec, const int32_t* plan,
+                               float2* image, float2* part, int32_t* wg_units, hipStream_t st) {
+    const dim3 g(workgroups), b(kThreads);
+    switch (cap) {
+#define KK_QUEUE_CASE(C)                                                                                        \
+    case C:                                                                                                     \
+        hipLaunchKernelGGL(gather_queue_kernel<C>, g, b, 0, st, tab, items, list_begin, counters, rec, plan, image, \
+                           part, wg_units);                                                                     \
+        break;
+        KK_QUEUE_CASE(64)
+        KK_QUEUE_CASE(128)
+        KK_QUEUE_CASE(192)
+        KK_QUEUE_CASE(256)
+        KK_QUEUE_CASE(320)
+        KK_QUEUE_CASE(384)
+        KK_QUEUE_CASE(448)
+        KK_QUEUE_CASE(512)
+#undef KK_QUEUE_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_grouped(const ReduceEntry* tab, const int32_t* blk, int blocks, const float2* part,
+                                 float2* image, float* inten, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_grouped, dim3(blocks), dim3(256), 0, st, tab, blk, part, image, inten);
+    return hipGetLastError();
+}
 
 size_t gather_workspace_bytes(const int32_t* h) {
     if (h[PW_SPLIT] <= 1) return 0;

@@ -159,17 +159,15 @@ __device__ __forceinline__ void chunk_mfma(floatx16 (&acc)[2], const ChunkOperan
 // phases) is written to LDS from its register stage, whose global loads were issued kStages-2
 // chunks earlier.  The results leave through LDS as 64-byte runs (8 bins of one (i, o)).
 template <int LOG2N>
-__global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
-                                                                     const int32_t* __restrict__ shift,
-                                                                     float2* __restrict__ Y, int ntx, int M,
-                                                                     int L, int ncol, int kpad) {
+__device__ __forceinline__ void contract_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
+                                              float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad,
+                                              int kb, int rt, int ct) {
     constexpr int N = 1 << LOG2N;
     __shared__ float2 fac[64 + N / 64];
     __shared__ __attribute__((aligned(16))) float xs[2][32 * kRowFloats];
     __shared__ float2 ws[2][kChunkL * kBinBlock * 16];            // [l][bin][angle]
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int kb = blockIdx.x, rt = blockIdx.y, ct = blockIdx.z;
     build_phase_factors<LOG2N>(fac, tid);
     // lane roles.  B (2 x 32): part = lane / 32 in {Re, Im}, transmit column lane % 32.
     // A (32 x 2): row lane % 32 = {Re rows 0..15, Im rows 16..31} x 16 receive angles; the lane
@@ -355,16 +353,15 @@ __device__ __forceinline__ void split_mfma(floatx16 (&acc)[2], const SplitOperan
 
 // Same workgroup shape and software pipeline as contract_kernel.
 template <int LOG2N, bool F16>
-__global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
-    const float2* __restrict__ X, const int32_t* __restrict__ shift, float2* __restrict__ Y, int ntx, int M, int L,
-    int ncol, int kpad, float xscale, float yscale) {
+__device__ __forceinline__ void contract_split_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
+                                                    float2* __restrict__ Y, int ntx, int M, int L, int ncol,
+                                                    int kpad, float xscale, float yscale, int kb, int rt, int ct) {
     constexpr int N = 1 << LOG2N;
     __shared__ float2 fac[64 + N / 64];
     __shared__ __attribute__((aligned(16))) uint32_t xs[2][32 * kXsWords];
     __shared__ __attribute__((aligned(16))) uint32_t ws[2][kBinBlock * 16 * 2 * kWsBlock];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int kb = blockIdx.x, rt = blockIdx.y, ct = blockIdx.z;
     build_phase_factors<LOG2N>(fac, tid);
     const int g = lane >> 5, col = lane & 31;
 
@@ -417,6 +414,56 @@ __global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
     }
 }
 
+template <int LOG2N>
+__global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
+                                                                     const int32_t* __restrict__ shift,
+                                                                     float2* __restrict__ Y, int ntx, int M,
+                                                                     int L, int ncol, int kpad) {
+    contract_body<LOG2N>(X, shift, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int LOG2N, bool F16>
+__global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
+    const float2* __restrict__ X, const int32_t* __restrict__ shift, float2* __restrict__ Y, int ntx, int M, int L,
+    int ncol, int kpad, float xscale, float yscale) {
+    contract_split_body<LOG2N, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
+                                    blockIdx.z);
+}
+
+// Grouped launches over the frames of one FFT-length class: block b runs block b - block0
+// of frame entry blk[b], in the per-frame grid order (bin block fastest, then receive tile,
+// then transmit tile).  PREC: 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo.
+template <int LOG2N, int PREC>
+__global__ __launch_bounds__(kContractThreads) void contract_grouped(const ContractEntry* __restrict__ tab,
+                                                                     const int32_t* __restrict__ blk,
+                                                                     float2* __restrict__ ws,
+                                                                     const int32_t* __restrict__ plan) {
+    const ContractEntry e = tab[blk[blockIdx.x]];
+    int local = (int)blockIdx.x - e.block0;
+    const int kb = local % e.nkb;
+    local /= e.nkb;
+    const int rt = local % e.nrt, ct = local / e.nrt;
+    if constexpr (PREC == 0)
+        contract_body<LOG2N>(ws + e.x_off, plan + e.shift_off, ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt,
+                             ct);
+    else
+        contract_split_body<LOG2N, PREC == 2>(ws + e.x_off, plan + e.shift_off, ws + e.y_off, e.ntx, e.M, e.L, e.ncol,
+                                              e.kpad, e.xscale, e.yscale, kb, rt, ct);
+}
+
+template <int LOG2N>
+hipError_t grouped_contract(int prec, const ContractEntry* tab, const int32_t* blk, int blocks, float2* ws,
+                            const int32_t* plan, hipStream_t st) {
+    const dim3 g(blocks), b(kContractThreads);
+    switch (prec) {
+        case KK_PREC_FP32: hipLaunchKernelGGL((contract_grouped<LOG2N, 0>), g, b, 0, st, tab, blk, ws, plan); break;
+        case KK_PREC_BF16X3: hipLaunchKernelGGL((contract_grouped<LOG2N, 1>), g, b, 0, st, tab, blk, ws, plan); break;
+        case KK_PREC_FP16X3: hipLaunchKernelGGL((contract_grouped<LOG2N, 2>), g, b, 0, st, tab, blk, ws, plan); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int LOG2N, bool F16>
 hipError_t contract_split(const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L, int ncol, int kpad,
                           float xscale, hipStream_t st) {
@@ -464,6 +511,30 @@ hipError_t launch_contract(int log2n, const float2* X, const int32_t* shift, flo
 }
 
 constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+
+hipError_t launch_contract_grouped(int log2n, int precision, const ContractEntry* tab, const int32_t* blk, int blocks,
+                                   float2* ws, const int32_t* plan, hipStream_t st) {
+    switch (log2n) {
+        case 8: return grouped_contract<8>(precision, tab, blk, blocks, ws, plan, st);
+        case 9: return grouped_contract<9>(precision, tab, blk, blocks, ws, plan, st);
+        case 10: return grouped_contract<10>(precision, tab, blk, blocks, ws, plan, st);
+        case 11: return grouped_contract<11>(precision, tab, blk, blocks, ws, plan, st);
+        case 12: return grouped_contract<12>(precision, tab, blk, blocks, ws, plan, st);
+        case 13: return grouped_contract<13>(precision, tab, blk, blocks, ws, plan, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int fp16_prescale_exponent(int T) {
+    // |X| <= 2 T 32768 (analytic mask x int16 record): 2^e X stays below 2^15
+    int e = 15;
+    for (int64_t bound = 2 * (int64_t)T * 32768; bound > 1; bound = (bound + 1) / 2) --e;
+    return e;
+}
+
+namespace {
 
 struct DecomposeLayout {
     int log2n, K, kpad, ncol;
@@ -538,9 +609,7 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
     } else if (precision == KK_PREC_BF16X3) {
         ce = launch_contract_split<false>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
     } else {
-        // |X| <= 2 T 32768 (analytic mask x int16 record): scale by 2^e so that it stays below 2^15
-        int e = 15;
-        for (int64_t bound = 2 * (int64_t)g->T * 32768; bound > 1; bound = (bound + 1) / 2) --e;
+        const int e = fp16_prescale_exponent(g->T);
         ce = launch_contract_split<true>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, std::ldexp(1.0f, e), st);
     }
     if (ce != hipSuccess) return KK_E_HIP;

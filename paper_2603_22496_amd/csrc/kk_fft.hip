@@ -226,16 +226,16 @@ __device__ __forceinline__ void middle_passes(float2* data, const float2* fac, i
 // One record pair per workgroup: the two real records are the real and imaginary parts of one
 // complex FFT.  The records enter LDS as 16-byte loads (8 samples), zero-padded to n; the
 // spectra leave as one 64-byte run (8 bins) per thread and record.
+// Body of record pair blk of one frame (shared by the per-frame and the grouped launches).
 template <int LOG2N, bool BLOCKED>
-__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
-                                                                  int T, float2* __restrict__ out, int L, int ncol,
-                                                                  int kpad) {
+__device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf, int ntraces, int T,
+                                                 float2* __restrict__ out, int L, int ncol, int kpad, int blk) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
     __shared__ __attribute__((aligned(16))) float2 data[N + N / 16];
     __shared__ float2 fac[64 + N / 64];
     const int tid = threadIdx.x;
-    const int t0 = 2 * blockIdx.x, t1 = t0 + 1;
+    const int t0 = 2 * blk, t1 = t0 + 1;
     const bool has1 = t1 < ntraces;
     make_factors<LOG2N>(fac, tid);
     const int16_t* a = rf + (size_t)t0 * T;
@@ -292,17 +292,16 @@ __global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t*
     }
 }
 
+// Body of record t of one frame.
 template <int LOG2N, bool NYQ>
-__global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* __restrict__ in, int kpad,
-                                                                  float2* __restrict__ out, int T,
-                                                                  NyquistSum nyq) {
+__device__ __forceinline__ void fft_inverse_body(const float2* __restrict__ in, int kpad, float2* __restrict__ out,
+                                                 int T, const NyquistSum& nyq, int t) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
     constexpr int K = N / 2 + 1;
     __shared__ float2 data[N + N / 16];
     __shared__ float2 fac[64 + N / 64];
     const int tid = threadIdx.x;
-    const int t = blockIdx.x;
     make_factors<LOG2N>(fac, tid);
     const float2* y = in + (size_t)t * kpad;
     float2 ynyq = make_float2(0.f, 0.f);
@@ -376,6 +375,42 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
     }
 }
 
+template <int LOG2N, bool BLOCKED>
+__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
+                                                                  int T, float2* __restrict__ out, int L, int ncol,
+                                                                  int kpad) {
+    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x);
+}
+
+template <int LOG2N, bool NYQ>
+__global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* __restrict__ in, int kpad,
+                                                                  float2* __restrict__ out, int T,
+                                                                  NyquistSum nyq) {
+    fft_inverse_body<LOG2N, NYQ>(in, kpad, out, T, nyq, blockIdx.x);
+}
+
+// Grouped launches over the frames of one FFT-length class: block b runs record pair (or
+// record) b - block0 of frame entry blk[b].
+template <int LOG2N>
+__global__ __launch_bounds__(kFftThreads) void fft_forward_grouped(const FwdEntry* __restrict__ tab,
+                                                                   const int32_t* __restrict__ blk,
+                                                                   const int16_t* __restrict__ rf,
+                                                                   float2* __restrict__ ws) {
+    const FwdEntry e = tab[blk[blockIdx.x]];
+    fft_forward_body<LOG2N, true>(rf + e.rf_off, e.ntraces, e.T, ws + e.x_off, e.L, e.ncol, e.kpad,
+                                  (int)blockIdx.x - e.block0);
+}
+
+template <int LOG2N>
+__global__ __launch_bounds__(kFftThreads) void fft_inverse_grouped(const InvEntry* __restrict__ tab,
+                                                                   const int32_t* __restrict__ blk,
+                                                                   float2* __restrict__ ws,
+                                                                   const int32_t* __restrict__ plan) {
+    const InvEntry e = tab[blk[blockIdx.x]];
+    const NyquistSum nyq{ws + e.x_off, plan + e.shift_off, e.M, e.L, e.ncol};
+    fft_inverse_body<LOG2N, true>(ws + e.y_off, e.kpad, ws + e.out_off, e.T, nyq, (int)blockIdx.x - e.block0);
+}
+
 template <int LOG2N>
 hipError_t fwd(const int16_t* rf, int ntraces, int T, float2* out, bool blocked, int L, int ncol, int kpad,
                hipStream_t st) {
@@ -413,6 +448,36 @@ hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, 
         case 13: return fwd<13>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_fft_forward_grouped(int log2n, const FwdEntry* tab, const int32_t* blk, int blocks,
+                                      const int16_t* rf, float2* ws, hipStream_t st) {
+    const dim3 g(blocks), b(kFftThreads);
+    switch (log2n) {
+        case 8: hipLaunchKernelGGL(fft_forward_grouped<8>, g, b, 0, st, tab, blk, rf, ws); break;
+        case 9: hipLaunchKernelGGL(fft_forward_grouped<9>, g, b, 0, st, tab, blk, rf, ws); break;
+        case 10: hipLaunchKernelGGL(fft_forward_grouped<10>, g, b, 0, st, tab, blk, rf, ws); break;
+        case 11: hipLaunchKernelGGL(fft_forward_grouped<11>, g, b, 0, st, tab, blk, rf, ws); break;
+        case 12: hipLaunchKernelGGL(fft_forward_grouped<12>, g, b, 0, st, tab, blk, rf, ws); break;
+        case 13: hipLaunchKernelGGL(fft_forward_grouped<13>, g, b, 0, st, tab, blk, rf, ws); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_inverse_grouped(int log2n, const InvEntry* tab, const int32_t* blk, int blocks, float2* ws,
+                                      const int32_t* plan, hipStream_t st) {
+    const dim3 g(blocks), b(kFftThreads);
+    switch (log2n) {
+        case 8: hipLaunchKernelGGL(fft_inverse_grouped<8>, g, b, 0, st, tab, blk, ws, plan); break;
+        case 9: hipLaunchKernelGGL(fft_inverse_grouped<9>, g, b, 0, st, tab, blk, ws, plan); break;
+        case 10: hipLaunchKernelGGL(fft_inverse_grouped<10>, g, b, 0, st, tab, blk, ws, plan); break;
+        case 11: hipLaunchKernelGGL(fft_inverse_grouped<11>, g, b, 0, st, tab, blk, ws, plan); break;
+        case 12: hipLaunchKernelGGL(fft_inverse_grouped<12>, g, b, 0, st, tab, blk, ws, plan); break;
+        case 13: hipLaunchKernelGGL(fft_inverse_grouped<13>, g, b, 0, st, tab, blk, ws, plan); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_fft_inverse(const float2* in, int ntraces, int kpad, int log2n, float2* out, int T,

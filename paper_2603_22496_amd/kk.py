@@ -26,10 +26,17 @@ SCHEME_SHIFTED, SCHEME_CONFOCAL, SCHEME_SAME, SCHEME_FULL_UNIFORM = 0, 1, 2, 3
 PREC_FP32, PREC_BF16X3, PREC_FP16X3 = 0, 1, 2
 COMPOUND_COHERENT, COMPOUND_INCOHERENT = 0, 1
 
+STAGE_FFT, STAGE_CONTRACT, STAGE_INVERSE, STAGE_GATHER, STAGE_REDUCE, STAGE_ALL = 1, 2, 4, 8, 16, 31
+ENSEMBLE_CLASSES = 8
+WINDOW_CLASSES = (64, 128, 192, 256, 320, 384, 448, 512)
+
 EXPORTS = [
     "kk_select_pairs", "kk_build_luts", "kk_build_das_rx", "kk_beamform_plan",
     "kk_decompose_workspace_bytes", "kk_decompose", "kk_beamform_workspace_bytes", "kk_beamform",
     "kk_compound", "das_plan", "das_workspace_bytes", "das_beamform", "kk_status_string",
+    "kk_ensemble_default_tuning", "kk_ensemble_plan", "kk_ensemble_query", "kk_ensemble_frame_query",
+    "kk_ensemble_run", "kk_ensemble_graph_create", "kk_ensemble_graph_launch", "kk_ensemble_graph_destroy",
+    "kk_ensemble_autotune",
 ]
 
 
@@ -47,6 +54,37 @@ class Geom(ctypes.Structure):
 class Grid(ctypes.Structure):
     _fields_ = [("X", ctypes.c_int32), ("Z", ctypes.c_int32), ("x0_m", ctypes.c_double),
                 ("dx_m", ctypes.c_double), ("z0_m", ctypes.c_double), ("dz_m", ctypes.c_double)]
+
+
+class EnsembleFrame(ctypes.Structure):
+    _fields_ = [("geom", Geom), ("N", ctypes.c_int32), ("M", ctypes.c_int32), ("tpad", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("shift_q", ctypes.c_void_p), ("plan", ctypes.c_void_p),
+                ("plan_bytes", ctypes.c_size_t)]
+
+
+class EnsembleTuning(ctypes.Structure):
+    _fields_ = [("pair_tile", ctypes.c_int32 * ENSEMBLE_CLASSES), ("queue", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+    def as_dict(self) -> dict:
+        return dict(pair_tile={WINDOW_CLASSES[c]: int(self.pair_tile[c]) for c in range(ENSEMBLE_CLASSES)},
+                    queue=int(self.queue))
+
+
+class EnsembleFrameInfo(ctypes.Structure):
+    _fields_ = [("rf_offset", ctypes.c_int64), ("image_offset", ctypes.c_int64),
+                ("intensity_offset", ctypes.c_int64), ("rf_theta_offset", ctypes.c_int64),
+                ("share_offset", ctypes.c_int64)] + \
+               [(n, ctypes.c_int32) for n in ("N", "L", "T", "M", "S", "X", "Z", "P", "tpad", "cap", "split",
+                                               "group", "mode", "plan_offset", "shift_offset", "reserved")]
+
+
+class EnsembleSizes(ctypes.Structure):
+    _fields_ = [("rf_elems", ctypes.c_int64), ("image_elems", ctypes.c_int64),
+                ("intensity_elems", ctypes.c_int64), ("ws_bytes", ctypes.c_int64),
+                ("units_offset", ctypes.c_int64), ("nframes", ctypes.c_int32), ("ngroups", ctypes.c_int32),
+                ("nlaunches", ctypes.c_int32), ("nunits", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -79,6 +117,18 @@ def lib():
             "das_plan": [_i32, ctypes.POINTER(Geom), _i32p, _i32p, _i32p, _i32, ctypes.POINTER(Grid), _vp, _sz,
                          _szp],
             "das_beamform": [_vp, _i32, ctypes.POINTER(Geom), _vp, _vp, _sz, _vp, _vp, _sz, _vp],
+            "kk_ensemble_plan": [ctypes.POINTER(EnsembleFrame), _i32, _i32, ctypes.POINTER(EnsembleTuning),
+                                 ctypes.c_int64, _vp, _sz, _szp],
+            "kk_ensemble_query": [_vp, _sz, ctypes.POINTER(EnsembleSizes)],
+            "kk_ensemble_frame_query": [_vp, _sz, _i32, ctypes.POINTER(EnsembleFrameInfo)],
+            "kk_ensemble_run": [_vp, _vp, _sz, _vp, _vp, _vp, _vp, _sz, _i32, _vp],
+            "kk_ensemble_graph_create": [_vp, _vp, _sz, _vp, _vp, _vp, _vp, _sz, _vp,
+                                         ctypes.POINTER(ctypes.c_void_p)],
+            "kk_ensemble_graph_launch": [_vp, _vp],
+            "kk_ensemble_graph_destroy": [_vp],
+            "kk_ensemble_autotune": [ctypes.POINTER(EnsembleFrame), _i32, _i32, ctypes.c_int64, _vp, _sz, _vp, _vp,
+                                     _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(EnsembleTuning),
+                                     ctypes.POINTER(ctypes.c_float)],
         }
         for name in EXPORTS:
             fn = getattr(L, name)
@@ -91,6 +141,8 @@ def lib():
         L.das_workspace_bytes.restype = _sz
         L.kk_beamform_workspace_bytes.argtypes = [_vp, _sz]
         L.kk_beamform_workspace_bytes.restype = _sz
+        L.kk_ensemble_default_tuning.argtypes = [ctypes.POINTER(EnsembleTuning)]
+        L.kk_ensemble_default_tuning.restype = None
         L.kk_status_string.argtypes = [_i32]
         L.kk_status_string.restype = ctypes.c_char_p
         _lib = L
@@ -316,3 +368,173 @@ def make_setup(w, with_das: bool = False, scheme=None, M=None, j_list=None) -> S
     if with_das:
         dp = das_plan(w.N, g, luts, build_das_rx(g, gr), gr)
     return Setup(g, gr, sel, luts, plan, w.N, Md, w.T, luts["tpad"], dp)
+
+
+# --------------------------------------------------------------------------- frame ensembles
+
+def default_tuning() -> EnsembleTuning:
+    t = EnsembleTuning()
+    lib().kk_ensemble_default_tuning(ctypes.byref(t))
+    return t
+
+
+@dataclass
+class EnsembleInput:
+    """One frame of an ensemble: its geometry, angle counts, shear table and beamforming plan
+    (host arrays from build_luts / beamform_plan) and the intensity mode (-1: none)."""
+    geom: Geom
+    N: int
+    M: int
+    tpad: int
+    shift: np.ndarray
+    plan: np.ndarray
+    mode: int = COMPOUND_INCOHERENT
+
+
+def setup_frame_input(su: "Setup", mode: int = COMPOUND_INCOHERENT) -> EnsembleInput:
+    return EnsembleInput(su.geom, su.N, su.M, su.tpad, np.ascontiguousarray(su.luts["shift"], dtype=np.int32),
+                         np.ascontiguousarray(su.plan, dtype=np.int32), mode)
+
+
+class Ensemble:
+    """A planned frame ensemble and its packed device buffers (channel data in, images and
+    intensities out, workspace).  frame_rf(f) / frame_image(f) / frame_intensity(f) are views
+    of frame f's slices."""
+
+    def __init__(self, inputs, precision: int = PREC_BF16X3, tuning: EnsembleTuning | None = None,
+                 spectra_budget: int = 0, device="cuda", allocate: bool = True):
+        self.inputs = list(inputs)
+        self.precision = precision
+        self.spectra_budget = int(spectra_budget)
+        self._keep = [(np.ascontiguousarray(x.shift, dtype=np.int32), np.ascontiguousarray(x.plan, dtype=np.int32))
+                      for x in self.inputs]
+        arr = (EnsembleFrame * len(self.inputs))()
+        for i, (x, (sh, pl)) in enumerate(zip(self.inputs, self._keep)):
+            arr[i] = EnsembleFrame(x.geom, x.N, x.M, x.tpad, x.mode, sh.ctypes.data, pl.ctypes.data, pl.nbytes)
+        self._frames = arr
+        self.tuning = tuning if tuning is not None else default_tuning()
+        self.device = device
+        self.plan_dev = None
+        self._plan()
+        if allocate:
+            self.allocate()
+
+    def _plan(self):
+        need = _sz(0)
+        args = [self._frames, len(self.inputs), self.precision, ctypes.byref(self.tuning), self.spectra_budget]
+        st = lib().kk_ensemble_plan(*args, None, 0, ctypes.byref(need))
+        if st != KK_E_CAPACITY:
+            _check("kk_ensemble_plan", st)
+        plan = np.zeros(need.value // 4, dtype=np.int32)
+        _check("kk_ensemble_plan", lib().kk_ensemble_plan(*args, plan.ctypes.data_as(_vp), plan.nbytes,
+                                                          ctypes.byref(need)))
+        self.plan_host = plan
+        self.sizes = EnsembleSizes()
+        _check("kk_ensemble_query", lib().kk_ensemble_query(plan.ctypes.data_as(_vp), plan.nbytes,
+                                                            ctypes.byref(self.sizes)))
+        self.info = []
+        for f in range(len(self.inputs)):
+            fi = EnsembleFrameInfo()
+            _check("kk_ensemble_frame_query", lib().kk_ensemble_frame_query(plan.ctypes.data_as(_vp), plan.nbytes,
+                                                                            f, ctypes.byref(fi)))
+            self.info.append(fi)
+
+    def allocate(self):
+        dev = self.device
+        s = self.sizes
+        self.rf = torch.zeros(max(int(s.rf_elems), 1), dtype=torch.int16, device=dev)
+        self.image = torch.zeros(max(int(s.image_elems), 1), dtype=torch.complex64, device=dev)
+        self.intensity = torch.zeros(max(int(s.intensity_elems), 1), dtype=torch.float32, device=dev)
+        self.ws = torch.zeros(max(int(s.ws_bytes), 1), dtype=torch.uint8, device=dev)
+        self.upload_plan()
+
+    def upload_plan(self):
+        if self.plan_dev is None or self.plan_dev.numel() < self.plan_host.size:
+            self.plan_dev = to_device(self.plan_host, self.device)
+        else:
+            self.plan_dev[: self.plan_host.size].copy_(torch.from_numpy(self.plan_host))
+
+    def retune(self, tuning: EnsembleTuning):
+        """Re-plan with new launch shapes (same frames), reallocating what grew."""
+        self.tuning = tuning
+        old_ws = self.ws.numel()
+        self._plan()
+        if int(self.sizes.ws_bytes) > old_ws:
+            self.ws = torch.zeros(int(self.sizes.ws_bytes), dtype=torch.uint8, device=self.device)
+        self.upload_plan()
+
+    # views
+    def frame_rf(self, f):
+        i = self.info[f]
+        n = i.N * i.L * i.T
+        return self.rf[i.rf_offset: i.rf_offset + n].view(i.N, i.L, i.T)
+
+    def frame_image(self, f):
+        i = self.info[f]
+        n = i.S * i.X * i.Z
+        return self.image[i.image_offset: i.image_offset + n].view(i.S, i.X, i.Z)
+
+    def frame_intensity(self, f):
+        i = self.info[f]
+        if i.intensity_offset < 0:
+            return None
+        return self.intensity[i.intensity_offset: i.intensity_offset + i.X * i.Z].view(i.X, i.Z)
+
+    def frame_rf_theta(self, f):
+        i = self.info[f]
+        n = i.N * i.M * i.T
+        b = i.rf_theta_offset * 8
+        return self.ws[b: b + n * 8].view(torch.complex64).view(i.N, i.M, i.T)
+
+    def unit_counts(self) -> np.ndarray:
+        """Per window class and workgroup: gather units taken in the last run [8][1024]."""
+        b = int(self.sizes.units_offset)
+        return self.ws[b: b + ENSEMBLE_CLASSES * 1024 * 4].view(torch.int32).view(ENSEMBLE_CLASSES, 1024).cpu().numpy()
+
+    def _bufs(self):
+        return (self.plan_host.ctypes.data_as(_vp), _dev(self.plan_dev), self.plan_host.nbytes, _dev(self.rf),
+                _dev(self.image), _dev(self.intensity), _dev(self.ws), self.ws.numel())
+
+    def run(self, stages: int = STAGE_ALL, stream=None):
+        _check("kk_ensemble_run", lib().kk_ensemble_run(*self._bufs(), stages, _stream(stream)))
+
+    def graph(self, stream) -> "EnsembleGraph":
+        h = ctypes.c_void_p(0)
+        _check("kk_ensemble_graph_create", lib().kk_ensemble_graph_create(*self._bufs(), _stream(stream),
+                                                                          ctypes.byref(h)))
+        return EnsembleGraph(h)
+
+    def autotune(self, reps: int = 3, stream=None):
+        """Measure launch shapes on the device (synchronous); re-plans with the best and returns
+        (tuning, gather + reduce microseconds).  The candidate plans and workspace are sized for
+        the largest pair split (8 shares per set), so that every candidate fits."""
+        t = EnsembleTuning()
+        ctypes.memmove(ctypes.byref(t), ctypes.byref(self.tuning), ctypes.sizeof(t))
+        us = ctypes.c_float(0)
+        units = sum(((i.X + 63) // 64) * ((i.Z + 15) // 16) * i.S for i in self.info)
+        plan_cap = self.plan_host.nbytes + 8 * 8 * units + (1 << 16)
+        scratch = torch.empty((plan_cap + 3) // 4, dtype=torch.int32, device=self.device)
+        ws_need = int(self.sizes.ws_bytes) + sum(8 * 8 * i.S * i.X * i.Z + 256 for i in self.info)
+        if self.ws.numel() < ws_need:
+            self.ws = torch.zeros(ws_need, dtype=torch.uint8, device=self.device)
+        _check("kk_ensemble_autotune",
+               lib().kk_ensemble_autotune(self._frames, len(self.inputs), self.precision, self.spectra_budget,
+                                          _dev(scratch), plan_cap, _dev(self.rf), _dev(self.image),
+                                          _dev(self.intensity), _dev(self.ws), self.ws.numel(), reps,
+                                          _stream(stream), ctypes.byref(t), ctypes.byref(us)))
+        del scratch
+        self.retune(t)
+        return t, float(us.value)
+
+
+class EnsembleGraph:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def launch(self, stream):
+        _check("kk_ensemble_graph_launch", lib().kk_ensemble_graph_launch(self.handle, _stream(stream)))
+
+    def destroy(self):
+        if self.handle:
+            _check("kk_ensemble_graph_destroy", lib().kk_ensemble_graph_destroy(self.handle))
+            self.handle = None
