@@ -70,6 +70,13 @@ def parse():
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle check of the timed frame")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the split-precision decomposition report on the large workload")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the batched frame-ensemble report")
+    ap.add_argument("--ensemble-frames", type=int, default=200)
+    ap.add_argument("--ensemble-steps", type=int, default=5, help="timed graph replays of the ensemble")
+    ap.add_argument("--ensemble-density", type=float, default=0.05,
+                    help="scatterers per lambda^2 of the ensemble medium (input generation cost only)")
+    ap.add_argument("--ensemble-budget-gb", type=float, default=4.0,
+                    help="workspace for the decomposition spectra of one frame group")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -127,6 +134,135 @@ def precision_report(kk, C, torch, np, args):
         }
         print("bench: precision %s decompose %.2f us" % (name, ms * 1e3), file=sys.stderr, flush=True)
     return out
+
+
+def _decompose_bytes(N, L, T, M, tpad):
+    """Algorithmic HBM bytes of one unfused decomposition: int16 records in, analytic spectra
+    out and in, sheared spectra out and in, RF_theta out."""
+    K = tpad // 2 + 1
+    return N * L * T * 2 + 2 * N * L * K * 8 + 2 * N * M * K * 8 + N * M * T * 8
+
+
+def ensemble_report(kk, C, torch, np, args):
+    """Batched form: an ensemble of uneven frames (64-192 elements, 15-75 transmits, 1-3 Eq. 6
+    sets at 4-16x compression, grids 128 x 256 to 384 x 768) imaging one speckle medium whose
+    scatterers move up to 50 um per frame; BF16 hi+lo decomposition, FP32 beamforming, Eq. 9
+    intensities.  Planned once, launch shapes autotuned on the device, then timed as graph
+    replays (all frames per replay).  Compared with the same frames through the per-frame entry
+    points on one stream (which must give identical images)."""
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    wls = C.ensemble_workloads(args.ensemble_frames, seed=4000)
+    med = C.ensemble_medium(wls, seed=4001, per_lambda2=args.ensemble_density)
+    sus = [kk.make_setup(w) for w in wls]
+    inputs = [kk.setup_frame_input(su, kk.COMPOUND_INCOHERENT) for su in sus]
+    E = kk.Ensemble(inputs, precision=kk.PREC_BF16X3, spectra_budget=int(args.ensemble_budget_gb * (1 << 30)))
+    t_plan = time.time() - t0
+    t0 = time.time()
+    for f, w in enumerate(wls):
+        E.frame_rf(f).copy_(torch.from_numpy(C.ensemble_dataset(w, med, f).rf))
+    torch.cuda.synchronize()
+    t_sim = time.time() - t0
+    print("bench: ensemble %d frames planned in %.1fs, simulated in %.1fs; %d groups, %d launches, %d units"
+          % (len(wls), t_plan, t_sim, E.sizes.ngroups, E.sizes.nlaunches, E.sizes.nunits), file=sys.stderr,
+          flush=True)
+    stream = torch.cuda.Stream()
+
+    def ev_time(fn, reps, warm=1):
+        for _ in range(warm):
+            fn()
+        stream.synchronize()
+        t = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            t.append(a.elapsed_time(b))
+        return float(np.median(t))
+
+    gather_stages = kk.STAGE_GATHER | kk.STAGE_REDUCE
+    dec_stages = kk.STAGE_FFT | kk.STAGE_CONTRACT | kk.STAGE_INVERSE
+    E.run(stream=stream)
+    ms_gather_default = ev_time(lambda: E.run(gather_stages, stream), 3)
+    default = E.tuning.as_dict()
+    t0 = time.time()
+    tuning, tuned_us = E.autotune(reps=3, stream=stream)
+    t_tune = time.time() - t0
+    print("bench: ensemble autotune %.1fs: %s, gather+reduce %.3f -> %.3f ms"
+          % (t_tune, tuning.as_dict(), ms_gather_default, tuned_us * 1e-3), file=sys.stderr, flush=True)
+    g = E.graph(stream)
+    try:
+        ms = ev_time(lambda: g.launch(stream), args.ensemble_steps, warm=2)
+    finally:
+        g.destroy()
+    ms_dec = ev_time(lambda: E.run(dec_stages, stream), 3)
+    ms_gat = ev_time(lambda: E.run(gather_stages, stream), 3)
+    E.run(stream=stream)
+    stream.synchronize()
+    print("bench: ensemble %.3f ms per replay (%.1f frames/s); decompose %.3f ms, gather+reduce %.3f ms"
+          % (ms, len(wls) * 1e3 / ms, ms_dec, ms_gat), file=sys.stderr, flush=True)
+
+    # the same frames through the per-frame entry points, with the ensemble's pair splits
+    SPLIT_WORD = 24
+    per = []
+    max_ws = max(kk.decompose_workspace_bytes(su.geom, su.N, su.M, su.tpad, kk.PREC_BF16X3) for su in sus)
+    dws = torch.empty(max_ws, dtype=torch.uint8, device=dev)
+    for f, su in enumerate(sus):
+        i = E.info[f]
+        plan = su.plan.copy()
+        plan[SPLIT_WORD] = i.split
+        bws = kk.beamform_workspace_bytes(plan)
+        per.append(dict(su=su, plan=plan, plan_dev=kk.to_device(plan), shift=kk.to_device(su.luts["shift"]),
+                        rt=torch.empty((su.N, su.M, su.T), dtype=torch.complex64, device=dev),
+                        img=torch.empty((i.S, i.X, i.Z), dtype=torch.complex64, device=dev),
+                        inten=torch.empty((i.X, i.Z), dtype=torch.float32, device=dev),
+                        bws=torch.empty(bws, dtype=torch.uint8, device=dev) if bws else None, rf=E.frame_rf(f)))
+
+    def per_frame_loop():
+        for d in per:
+            su = d["su"]
+            kk.decompose(d["rf"], su.geom, d["shift"], su.M, su.tpad, out=d["rt"], ws=dws,
+                         precision=kk.PREC_BF16X3, stream=stream)
+            kk.beamform(d["rt"], d["plan"], d["plan_dev"], image=d["img"], intensity=d["inten"],
+                        mode=kk.COMPOUND_INCOHERENT, ws=d["bws"], stream=stream)
+
+    ms_loop = ev_time(per_frame_loop, 2)
+    stream.synchronize()
+    same = sum(int(torch.equal(d["img"], E.frame_image(f)) and torch.equal(d["inten"], E.frame_intensity(f)))
+               for f, d in enumerate(per))
+    pixpair = sum(i.X * i.Z * i.P for i in E.info)
+    dec_bytes = sum(_decompose_bytes(i.N, i.L, i.T, i.M, i.tpad) for i in E.info)
+    return {
+        "workload": "%d uneven frames: 64-192 el, 15-75 tx in +-10..18 deg, Eq.6 J=1-3 sets at 4-16x, "
+                    "grids 128x256..384x768 px, one speckle medium (%.2f/lambda^2) moving <=50 um/frame"
+                    % (len(wls), args.ensemble_density),
+        "precision": "bf16x3 decomposition, f32 beamform, Eq.9 intensities",
+        "frames": len(wls),
+        "pixel_pairs": pixpair,
+        "ms_per_ensemble": round(ms, 4),
+        "frames_per_s": round(len(wls) * 1e3 / ms, 1),
+        "gpixpair_per_s": round(pixpair / (ms * 1e-3) / 1e9, 2),
+        "stages_ms": {"decompose": round(ms_dec, 4), "gather_reduce": round(ms_gat, 4)},
+        "graph_launches": int(E.sizes.nlaunches) + sum(1 for c in set(i.cap for i in E.info)),
+        "decompose_groups": int(E.sizes.ngroups),
+        "gather_units": int(E.sizes.nunits),
+        "tuning_default": default,
+        "tuning": tuning.as_dict(),
+        "gather_reduce_ms_default_tuning": round(ms_gather_default, 4),
+        "gather_reduce_ms_tuned": round(tuned_us * 1e-3, 4),
+        "per_frame_loop_ms": round(ms_loop, 4),
+        "speedup_vs_per_frame_loop": round(ms_loop / ms, 2),
+        "frames_identical_to_per_frame_path": "%d/%d" % (same, len(wls)),
+        "stage_rooflines": {
+            "decompose": {"bound": "hbm", "bytes_unfused": dec_bytes,
+                          "frac_unfused": round(dec_bytes / HBM_BYTES_PER_S / (ms_dec * 1e-3), 4)},
+            "gather": {"bound": "alu", "lane_ops": OPS_PER_PIXEL_PAIR * pixpair,
+                       "frac": round(OPS_PER_PIXEL_PAIR * pixpair / VALU_LANE_OPS / (ms_gat * 1e-3), 4)},
+        },
+        "setup_s": {"plan": round(t_plan, 1), "simulate": round(t_sim, 1), "autotune": round(t_tune, 1)},
+    }
 
 
 def main():
@@ -207,6 +343,9 @@ def main():
 
     if not args.no_precision:
         res["precision"] = precision_report(kk, C, torch, np, args)
+
+    if not args.no_ensemble:
+        res["ensemble"] = ensemble_report(kk, C, torch, np, args)
 
     if args.copy_mb > 0:
         src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
@@ -291,6 +430,8 @@ def main():
     }
     if "precision" in res:
         out["precision_large"] = res["precision"]
+    if "ensemble" in res:
+        out["ensemble"] = res["ensemble"]
     if "das_ms" in res:
         das_units = w.X * w.Z * w.N * w.L                 # pixel x (transmit, element) gathers
         out["stage_rooflines"]["das"] = {
