@@ -16,6 +16,9 @@ It is a plain, slow, step-by-step FP64 statement of what the method computes
   decompose.py   Eq. 3 receive plane-wave decomposition by the Fourier shift theorem
   beamform.py    Eq. 5 (KK) and Eq. 4 (DAS) delay-gather sums
   compound.py    Eq. 8 / Eq. 9 compounding, |B|^2
+  completion.py  the k-space completion network on the per-bin pair grid (convolutions,
+                 gradients, masked loss, Adam, grid preparation and merge); imported as
+                 oracle.completion, not re-exported here
 
 Conventions the paper leaves open are fixed in each module's docstring.  Every function
 states the passage it follows.  Pins (tests marked "not gpu") check each step against
