@@ -403,6 +403,113 @@ int32_t kk_ensemble_autotune(const kk_ensemble_frame* frames, int32_t nframes, i
                              size_t ws_bytes, int32_t reps, void* stream,
                              kk_ensemble_tuning* tuning, float* best_us);
 
+/* =======================================================================================
+ * Spectra: the decomposition stopped before its inverse transform, and the inverse alone.
+ * ===================================================================================== */
+
+/* kk_spectrum_bins (host) - bins per record of a spectrum for FFT length tpad:
+ * kpad = tpad/2 + 1 rounded up to a multiple of 8; 0 if tpad is not a supported length. */
+int32_t kk_spectrum_bins(int32_t tpad);
+
+/* kk_decompose_spectrum (device) - the per-bin contraction of kk_decompose (Eq. 3 via the
+ * Fourier shift, analytic mask as there), without the inverse transform:
+ *   spec[i][o][k] = sum_l A[i][l][k] exp(2 pi i ((k shift_q[o][l]) mod (tpad 2^22)) / (tpad 2^22))
+ * for k < tpad/2; bins tpad/2 .. kpad-1 are set to zero.
+ *   spec   dev out complex float [N][M][kpad], kpad = kk_spectrum_bins(tpad)
+ *   ws     dev workspace of at least kk_decompose_workspace_bytes(g, N, M, tpad, precision)
+ * Other arguments, limits and errors as kk_decompose. */
+int32_t kk_decompose_spectrum(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q,
+                              int32_t M, int32_t tpad, int32_t precision, float* spec, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* kk_spectrum_inverse (device) - rf_theta[t][n] = (1/tpad) sum_{k <= tpad/2} spec[t][k]
+ * exp(+2 pi i k n / tpad), n < T, for ntraces records of kpad bins (the inverse transform of
+ * kk_decompose; bin tpad/2 taken from spec).
+ *   spec dev in complex float [ntraces][kpad];  rf_theta dev out complex float [ntraces][T]
+ * Errors: KK_E_NULL, KK_E_ARG (sizes, tpad not a supported length, T > tpad), KK_E_HIP. */
+int32_t kk_spectrum_inverse(const float* spec, int32_t ntraces, int32_t tpad, int32_t T,
+                            float* rf_theta, void* stream);
+
+/* =======================================================================================
+ * Learned k-space completion (a network on the per-bin pair grid).
+ *
+ * One bin k of a decomposition spectrum over a uniform receive bank is a complex grid of
+ * H transmit angles x W receive angles; every (theta_i, theta_o) pair is one k-space sample
+ * (Sec. II-B).  A compressive acquisition observes J of the W receive columns.  The network
+ * (KK_NET_LAYERS 3x3 convolutions, KK_NET_WIDTH channels, ReLU between them; BF16 weights
+ * and activations, FP32 accumulation on MFMA, FP32 master parameters and Adam moments)
+ * maps the observed grid to the full grid:
+ *   grid  [B][H][W][KK_NET_IN] BF16: c0, c1 = Re, Im of the observed pairs / scale (0 where
+ *         unobserved), c2 = 1 where observed, c3..7 = 0; scale = RMS of the observed pairs
+ *   out   [B][H][W][2] FP32: the predicted grid / scale
+ * and the completed spectrum keeps every observed pair and takes out * scale elsewhere.
+ * Training minimises the mean squared error over unobserved pairs (Adam).
+ * Parameters (FP32, kk_net_param_count of them): per layer l the weights W[9][32][cin]
+ * (tap t = 3 (dy+1) + (dx+1), output channel, input channel; cin = KK_NET_IN for l = 0,
+ * KK_NET_WIDTH after) then the bias [32]; the last layer's output channels 2..31 must be zero.
+ * Limits: 16 <= W <= 192 with W a multiple of 16; H >= 1; B >= 1.
+ * ===================================================================================== */
+#define KK_NET_LAYERS 6
+#define KK_NET_WIDTH 32
+#define KK_NET_IN 8
+
+enum { KK_NET_PARAMS = 0, KK_NET_GRADS = 1, KK_NET_MOMENT1 = 2, KK_NET_MOMENT2 = 3 };
+
+/* Sizes: parameters, the device state (parameters, gradient, moments, BF16 weights), and the
+ * workspace of a batch of B grids of H x W (0 if the shape is not supported). */
+size_t kk_net_param_count(void);
+size_t kk_net_state_bytes(void);
+size_t kk_net_workspace_bytes(int32_t B, int32_t H, int32_t W);
+
+/* kk_net_load (host, synchronous) - parameters from host memory into the device state; Adam
+ * moments and gradient zeroed; BF16 weights built.  kk_net_read (host, synchronous) - copy
+ * the parameters, gradient or moments (KK_NET_*) back.  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
+int32_t kk_net_load(void* state, const float* params_host, void* stream);
+int32_t kk_net_read(const void* state, int32_t what, float* host, void* stream);
+
+/* kk_net_prepare (device) - input grids (and training targets) of B bins of a spectrum
+ * spec [H][Msrc][kpad]: sample b is bin bins[b] (dev, or k_first + b when bins is NULL); grid
+ * column w is observed when grid_to_obs[w] = j >= 0, with the value spec[h][obs_src[j]][k];
+ * target (dev [B][H][W][2] or NULL; needs Msrc == W) = spec[h][w][k] / scale; scale dev [B].
+ * obs_src [J], grid_to_obs [W]: dev int32.  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
+int32_t kk_net_prepare(const float* spec, int32_t H, int32_t Msrc, int32_t kpad, const int32_t* bins,
+                       int32_t k_first, int32_t B, const int32_t* obs_src, int32_t J,
+                       const int32_t* grid_to_obs, int32_t W, uint16_t* grid, float* target,
+                       float* scale, void* stream);
+
+/* kk_net_forward (device) - out = network(grid); batch row b reads grid sample sidx[b] (dev,
+ * or b when sidx is NULL).  ws: kk_net_workspace_bytes(B, H, W).
+ * Errors: KK_E_NULL, KK_E_ARG (shape), KK_E_WORKSPACE, KK_E_HIP. */
+int32_t kk_net_forward(const void* state, const uint16_t* grid, const int32_t* sidx, int32_t B,
+                       int32_t H, int32_t W, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* kk_net_backward (device) - forward pass, loss and parameter gradient of a batch:
+ *   loss (dev float) = inv_count * sum over unobserved pairs of |out - target|^2
+ * (inv_count = 1 / (2 x unobserved pairs in the batch)); target dev [*][H][W][2] indexed like
+ * grid.  The gradient stays in the state (kk_net_read KK_NET_GRADS).  kk_net_adam (device) -
+ * one Adam update (b1 0.9, b2 0.999, eps 1e-8, step >= 1) from that gradient, then the BF16
+ * weights.  kk_net_train_step = kk_net_backward + kk_net_adam.
+ * Errors: KK_E_NULL, KK_E_ARG, KK_E_WORKSPACE, KK_E_HIP. */
+int32_t kk_net_backward(void* state, const uint16_t* grid, const float* target, const int32_t* sidx,
+                        int32_t B, int32_t H, int32_t W, float inv_count, float* loss, void* ws,
+                        size_t ws_bytes, void* stream);
+int32_t kk_net_adam(void* state, int32_t step, float lr, void* stream);
+int32_t kk_net_train_step(void* state, const uint16_t* grid, const float* target, const int32_t* sidx,
+                          int32_t B, int32_t H, int32_t W, float inv_count, int32_t step, float lr,
+                          float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* kk_net_merge (device) - completed spectrum of B bins: dst[h][w][k] = spec[h][obs_src[j]][k]
+ * where column w is observed (j = grid_to_obs[w] >= 0), else out[b][h][w] * scale[b]; dst dev
+ * complex float [H][W][kpad] (other bins untouched).  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
+int32_t kk_net_merge(const float* out, const float* scale, const int32_t* bins, int32_t k_first,
+                     int32_t B, const float* spec, int32_t H, int32_t Msrc, int32_t kpad,
+                     const int32_t* obs_src, const int32_t* grid_to_obs, int32_t W, float* dst,
+                     void* stream);
+
+/* kk_clear (device) - zero `bytes` bytes at dev (16-byte aligned, a multiple of 16), by a
+ * kernel (so that it may be captured into a graph).  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
+int32_t kk_clear(void* dev, size_t bytes, void* stream);
+
 /* Human-readable name of a kk_status value (static string, never NULL). */
 const char* kk_status_string(int32_t status);
 

@@ -527,6 +527,17 @@ hipError_t launch_contract_grouped(int log2n, int precision, const ContractEntry
     }
 }
 
+namespace {
+// bins [from, kpad) of every record of y [n][kpad] set to zero
+__global__ void zero_bins_kernel(float2* __restrict__ y, int64_t n, int kpad, int from) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int width = kpad - from;
+    if (i >= n * width) return;
+    const int64_t r = i / width;
+    y[r * kpad + from + (int)(i - r * width)] = make_float2(0.f, 0.f);
+}
+}  // namespace
+
 int fp16_prescale_exponent(int T) {
     // |X| <= 2 T 32768 (analytic mask x int16 record): 2^e X stays below 2^15
     int e = 15;
@@ -618,6 +629,58 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
         hipSuccess)
         return KK_E_HIP;
     return KK_OK;
+}
+
+int32_t kk_spectrum_bins(int32_t tpad) {
+    const int lg = kk::log2_exact(tpad);
+    if (lg < kk::kMinLog2Fft || lg > kk::kMaxLog2Fft) return 0;
+    return (tpad / 2 + 1 + kk::kBinBlock - 1) / kk::kBinBlock * kk::kBinBlock;
+}
+
+int32_t kk_decompose_spectrum(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M,
+                              int32_t tpad, int32_t precision, float* spec, void* ws, size_t ws_bytes, void* stream) {
+    using namespace kk;
+    if (!rf || !g || !shift_q || !spec || !ws) return KK_E_NULL;
+    if (precision != KK_PREC_FP32 && precision != KK_PREC_BF16X3 && precision != KK_PREC_FP16X3)
+        return KK_E_UNSUPPORTED;
+    if (N < 1 || M < 1 || g->L < 1 || g->L > 65536 || g->T < 1) return KK_E_ARG;
+    DecomposeLayout d;
+    if (!decompose_layout(g, N, M, tpad, &d)) return KK_E_ARG;
+    if ((int64_t)N * g->L > 0x7fffffff || (int64_t)N * M > 0x7fffffff) return KK_E_ARG;
+    if (ws_bytes < d.y_off) return KK_E_WORKSPACE;  // the spectra only; Y is the caller's
+    hipStream_t st = (hipStream_t)stream;
+    float2* X = static_cast<float2*>(ws);
+    float2* Y = reinterpret_cast<float2*>(spec);
+    if (launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st) != hipSuccess)
+        return KK_E_HIP;
+    hipError_t ce;
+    if (precision == KK_PREC_FP32) {
+        ce = launch_contract(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, st);
+    } else if (precision == KK_PREC_BF16X3) {
+        ce = launch_contract_split<false>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
+    } else {
+        ce = launch_contract_split<true>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad,
+                                         std::ldexp(1.0f, fp16_prescale_exponent(g->T)), st);
+    }
+    if (ce != hipSuccess) return KK_E_HIP;
+    const int from = tpad / 2;
+    const int64_t n = (int64_t)N * M * (d.kpad - from);
+    hipLaunchKernelGGL(zero_bins_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Y, (int64_t)N * M,
+                       d.kpad, from);
+    return hipGetLastError() == hipSuccess ? KK_OK : KK_E_HIP;
+}
+
+int32_t kk_spectrum_inverse(const float* spec, int32_t ntraces, int32_t tpad, int32_t T, float* rf_theta,
+                            void* stream) {
+    using namespace kk;
+    if (!spec || !rf_theta) return KK_E_NULL;
+    const int lg = log2_exact(tpad);
+    if (ntraces < 1 || T < 1 || T > tpad || lg < kMinLog2Fft || lg > kMaxLog2Fft) return KK_E_ARG;
+    const int kpad = kk_spectrum_bins(tpad);
+    return launch_fft_inverse(reinterpret_cast<const float2*>(spec), ntraces, kpad, lg,
+                              reinterpret_cast<float2*>(rf_theta), T, (hipStream_t)stream) == hipSuccess
+               ? KK_OK
+               : KK_E_HIP;
 }
 
 size_t das_workspace_bytes(const kk_geom* g, int32_t N, const void* plan_host, size_t plan_bytes) {

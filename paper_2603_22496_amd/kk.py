@@ -37,7 +37,13 @@ EXPORTS = [
     "kk_ensemble_default_tuning", "kk_ensemble_plan", "kk_ensemble_query", "kk_ensemble_frame_query",
     "kk_ensemble_run", "kk_ensemble_graph_create", "kk_ensemble_graph_launch", "kk_ensemble_graph_destroy",
     "kk_ensemble_autotune",
+    "kk_spectrum_bins", "kk_decompose_spectrum", "kk_spectrum_inverse",
+    "kk_net_param_count", "kk_net_state_bytes", "kk_net_workspace_bytes", "kk_net_load", "kk_net_read",
+    "kk_net_prepare", "kk_net_forward", "kk_net_backward", "kk_net_adam", "kk_net_train_step", "kk_net_merge",
+    "kk_clear",
 ]
+NET_LAYERS, NET_WIDTH, NET_IN = 6, 32, 8
+NET_PARAMS, NET_GRADS, NET_MOMENT1, NET_MOMENT2 = 0, 1, 2, 3
 
 
 class KKError(RuntimeError):
@@ -126,6 +132,19 @@ def lib():
                                          ctypes.POINTER(ctypes.c_void_p)],
             "kk_ensemble_graph_launch": [_vp, _vp],
             "kk_ensemble_graph_destroy": [_vp],
+            "kk_spectrum_bins": [_i32],
+            "kk_decompose_spectrum": [_vp, _i32, ctypes.POINTER(Geom), _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp],
+            "kk_spectrum_inverse": [_vp, _i32, _i32, _i32, _vp, _vp],
+            "kk_net_load": [_vp, _vp, _vp],
+            "kk_net_read": [_vp, _i32, _vp, _vp],
+            "kk_net_prepare": [_vp, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp],
+            "kk_net_forward": [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp],
+            "kk_net_backward": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, ctypes.c_float, _vp, _vp, _sz, _vp],
+            "kk_net_adam": [_vp, _i32, ctypes.c_float, _vp],
+            "kk_net_train_step": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, ctypes.c_float, _i32, ctypes.c_float, _vp,
+                                  _vp, _sz, _vp],
+            "kk_net_merge": [_vp, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp],
+            "kk_clear": [_vp, _sz, _vp],
             "kk_ensemble_autotune": [ctypes.POINTER(EnsembleFrame), _i32, _i32, ctypes.c_int64, _vp, _sz, _vp, _vp,
                                      _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(EnsembleTuning),
                                      ctypes.POINTER(ctypes.c_float)],
@@ -141,6 +160,11 @@ def lib():
         L.das_workspace_bytes.restype = _sz
         L.kk_beamform_workspace_bytes.argtypes = [_vp, _sz]
         L.kk_beamform_workspace_bytes.restype = _sz
+        for name in ("kk_net_param_count", "kk_net_state_bytes"):
+            getattr(L, name).argtypes = []
+            getattr(L, name).restype = _sz
+        L.kk_net_workspace_bytes.argtypes = [_i32, _i32, _i32]
+        L.kk_net_workspace_bytes.restype = _sz
         L.kk_ensemble_default_tuning.argtypes = [ctypes.POINTER(EnsembleTuning)]
         L.kk_ensemble_default_tuning.restype = None
         L.kk_status_string.argtypes = [_i32]
@@ -333,6 +357,132 @@ def das_beamform(rf, g: Geom, plan_host: np.ndarray, plan_dev, image=None, ws=No
                             _stream(stream))
     _check("das_beamform", st)
     return image
+
+
+def spectrum_bins(tpad: int) -> int:
+    return int(lib().kk_spectrum_bins(tpad))
+
+
+def decompose_spectrum(rf, g: Geom, shift_q, M: int, tpad: int, out=None, ws=None, precision: int = PREC_FP32,
+                       stream=None):
+    """rf int16 [N][L][T], shift_q int32 [M][L] on the device -> complex64 [N][M][kpad] (bins >= tpad/2 zero)."""
+    N = rf.shape[0]
+    kpad = spectrum_bins(tpad)
+    if out is None:
+        out = torch.empty((N, M, kpad), dtype=torch.complex64, device=rf.device)
+    nbytes = decompose_workspace_bytes(g, N, M, tpad, precision)
+    if ws is None:
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=rf.device)
+    _check("kk_decompose_spectrum", lib().kk_decompose_spectrum(_dev(rf), N, ctypes.byref(g), _dev(shift_q), M, tpad,
+                                                                precision, _dev(out), _dev(ws),
+                                                                ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
+def spectrum_inverse(spec, tpad: int, T: int, out=None, stream=None):
+    """spec complex64 [..., kpad] -> complex64 [..., T] (first T samples of the inverse transform)."""
+    lead = spec.shape[:-1]
+    n = int(np.prod(lead))
+    if out is None:
+        out = torch.empty(tuple(lead) + (T,), dtype=torch.complex64, device=spec.device)
+    _check("kk_spectrum_inverse", lib().kk_spectrum_inverse(_dev(spec), n, tpad, T, _dev(out), _stream(stream)))
+    return out
+
+
+def clear(t, stream=None):
+    _check("kk_clear", lib().kk_clear(_dev(t), t.numel() * t.element_size(), _stream(stream)))
+
+
+def net_param_count() -> int:
+    return int(lib().kk_net_param_count())
+
+
+def net_layer_shapes():
+    """[(cin, offset of W, offset of bias)] per layer of the flat FP32 parameter vector."""
+    out, off = [], 0
+    for l in range(NET_LAYERS):
+        cin = NET_IN if l == 0 else NET_WIDTH
+        out.append((cin, off, off + 9 * NET_WIDTH * cin))
+        off += 9 * NET_WIDTH * cin + NET_WIDTH
+    assert off == net_param_count()
+    return out
+
+
+class Net:
+    """Device state of the completion network (parameters, Adam moments, gradient, BF16
+    weights) and its workspace for batches of up to B grids of H x W."""
+
+    def __init__(self, params: np.ndarray, B: int, H: int, W: int, device="cuda"):
+        self.B, self.H, self.W = B, H, W
+        self.state = torch.zeros(int(lib().kk_net_state_bytes()), dtype=torch.uint8, device=device)
+        nb = int(lib().kk_net_workspace_bytes(B, H, W))
+        if nb == 0:
+            raise ValueError("unsupported grid shape %dx%d" % (H, W))
+        self.ws = torch.zeros(nb, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.step = 0
+        self.load(params)
+
+    def load(self, params: np.ndarray, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != net_param_count():
+            raise ValueError("expected %d parameters" % net_param_count())
+        _check("kk_net_load", lib().kk_net_load(_dev(self.state), p.ctypes.data, _stream(stream)))
+        self.step = 0
+
+    def read(self, what: int = NET_PARAMS, stream=None) -> np.ndarray:
+        out = np.zeros(net_param_count(), dtype=np.float32)
+        _check("kk_net_read", lib().kk_net_read(_dev(self.state), what, out.ctypes.data, _stream(stream)))
+        return out
+
+    def forward(self, grid, out, B=None, sidx=None, stream=None):
+        B = self.B if B is None else B
+        _check("kk_net_forward", lib().kk_net_forward(_dev(self.state), _dev(grid), _dev(sidx) if sidx is not None
+                                                      else None, B, self.H, self.W, _dev(out), _dev(self.ws),
+                                                      self.ws.numel(), _stream(stream)))
+        return out
+
+    def backward(self, grid, target, inv_count: float, B=None, sidx=None, stream=None):
+        B = self.B if B is None else B
+        _check("kk_net_backward", lib().kk_net_backward(_dev(self.state), _dev(grid), _dev(target),
+                                                        _dev(sidx) if sidx is not None else None, B, self.H, self.W,
+                                                        inv_count, _dev(self.loss), _dev(self.ws), self.ws.numel(),
+                                                        _stream(stream)))
+        return self.loss
+
+    def adam(self, lr: float, stream=None):
+        self.step += 1
+        _check("kk_net_adam", lib().kk_net_adam(_dev(self.state), self.step, lr, _stream(stream)))
+
+    def train_step(self, grid, target, inv_count: float, lr: float, B=None, sidx=None, stream=None):
+        B = self.B if B is None else B
+        self.step += 1
+        _check("kk_net_train_step", lib().kk_net_train_step(_dev(self.state), _dev(grid), _dev(target),
+                                                            _dev(sidx) if sidx is not None else None, B, self.H,
+                                                            self.W, inv_count, self.step, lr, _dev(self.loss),
+                                                            _dev(self.ws), self.ws.numel(), _stream(stream)))
+        return self.loss
+
+
+def net_prepare(spec, obs_src, grid_to_obs, grid, scale, bins=None, k_first: int = 0, B=None, target=None,
+                stream=None):
+    """Input grids (and targets) from spec complex64 [H][Msrc][kpad] (see kk_net_prepare)."""
+    H, Msrc, kpad = spec.shape
+    W = grid_to_obs.numel()
+    B = (bins.numel() if bins is not None else grid.shape[0]) if B is None else B
+    _check("kk_net_prepare", lib().kk_net_prepare(_dev(spec), H, Msrc, kpad, _dev(bins) if bins is not None else None,
+                                                  k_first, B, _dev(obs_src), obs_src.numel(), _dev(grid_to_obs), W,
+                                                  _dev(grid), _dev(target) if target is not None else None,
+                                                  _dev(scale), _stream(stream)))
+
+
+def net_merge(out, scale, spec, obs_src, grid_to_obs, dst, bins=None, k_first: int = 0, B=None, stream=None):
+    H, Msrc, kpad = spec.shape
+    W = grid_to_obs.numel()
+    B = (bins.numel() if bins is not None else out.shape[0]) if B is None else B
+    _check("kk_net_merge", lib().kk_net_merge(_dev(out), _dev(scale), _dev(bins) if bins is not None else None,
+                                              k_first, B, _dev(spec), H, Msrc, kpad, _dev(obs_src),
+                                              _dev(grid_to_obs), W, _dev(dst), _stream(stream)))
 
 
 def to_device(a: np.ndarray, device="cuda"):
