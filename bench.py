@@ -77,6 +77,9 @@ def parse():
                     help="scatterers per lambda^2 of the ensemble medium (input generation cost only)")
     ap.add_argument("--ensemble-budget-gb", type=float, default=4.0,
                     help="workspace for the decomposition spectra of one frame group")
+    ap.add_argument("--no-completion", action="store_true", help="skip the k-space completion report")
+    ap.add_argument("--completion-eval", type=int, default=8, help="evaluation phantoms of the completion report")
+    ap.add_argument("--no-study", action="store_true", help="skip the scheme / compounding image-metric study")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (HBM byte-counter calibration)")
     return ap.parse_args()
@@ -265,6 +268,80 @@ def ensemble_report(kk, C, torch, np, args):
     }
 
 
+def completion_report(kk, C, torch, np, args):
+    """k-space completion on the vernier geometry (13 of 128 bank columns observed): images of
+    evaluation phantoms (seeds 12000..) from plain compressed KK and from the completed spectrum,
+    against the fully sampled 128-angle KK image (GPU FP32, all pixels; FP64 oracle at sampled
+    pixels for two phantoms), with the trained weights committed in the package."""
+    from paper_2603_22496_amd import completion as CP
+    import oracle as O
+    cs = CP.setup()
+    d = CP.Device(cs)
+    loaded = CP.load()
+    W = len(cs.full.sel["rx_theta"])
+    net = kk.Net(loaded[0], CP.BATCH, cs.w.N, W, dilation=loaded[1].get("dilation")) if loaded else None
+    meta = loaded[1] if loaded else None
+    use_net = bool(meta and meta.get("use_net"))
+    errs = {"compressed": [], "compressed_best_gain": [], "completed": [], "completed_best_gain": []}
+    errs64 = {"compressed_best_gain": [], "completed": []}
+    rng = np.random.default_rng(5)
+    for e in range(args.completion_eval):
+        seed = CP.EVAL_SEED0 + e
+        ds = CP.phantom(cs, seed, meta["scatterers"] if meta else 1000)
+        rf = kk.to_device(ds.rf)
+        ref = CP.full_image(cs, d, rf).cpu().numpy()
+        comp = CP.complete_image(cs, d, rf, None).cpu().numpy()
+        a, b = CP.scaled_error(comp, ref)
+        errs["compressed"].append(a)
+        errs["compressed_best_gain"].append(b)
+        done = None
+        if net is not None:
+            done = CP.complete_image(cs, d, rf, net).cpu().numpy()
+            a, b = CP.scaled_error(done, ref)
+            errs["completed"].append(a)
+            errs["completed_best_gain"].append(b)
+        if e < 2 and not args.no_parity:   # the oracle checks the outputs; it produces none of them
+            xi, zi = rng.integers(0, cs.w.X, 300), rng.integers(0, cs.w.Z, 300)
+            su = cs.full
+            R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+            r64 = O.kk_beamform(R, su.sel["pairs"], 1, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                                su.luts["lut4"], su.luts["t0_q"], cs.w.X, cs.w.Z, pixels=(xi, zi))[0]
+            errs64["compressed_best_gain"].append(CP.scaled_error(comp[0, xi, zi], r64)[1])
+            if done is not None:
+                errs64["completed"].append(CP.scaled_error(done[0, xi, zi], r64)[0])
+    rf = kk.to_device(CP.phantom(cs, CP.EVAL_SEED0, 300).rf)
+    ms_c = timed(lambda: CP.complete_image(cs, d, rf, None), 5, 2, torch)
+    ms_n = timed(lambda: CP.complete_image(cs, d, rf, net), 3, 1, torch) if net is not None else None
+    mean = lambda v: round(float(np.mean(v)), 4) if v else None
+    out = {
+        "workload": "vernier geometry (128 el, 31 tx, 2048 samples, 256x512 px); 128-angle bank, 13 columns "
+                    "observed (403 of 3968 pairs, 9.8x); 6x3x3 conv, 32 ch, BF16/FP32 on MFMA",
+        "eval_phantoms": args.completion_eval,
+        "rel_l2_vs_fully_sampled_gpu": {k: mean(v) for k, v in errs.items()},
+        "rel_l2_vs_fp64_fully_sampled_sampled_pixels": {k: mean(v) for k, v in errs64.items()},
+        "product_path": "network" if use_net else "fallback: plain compressed KK",
+        "ms_per_frame": {"compressed": round(ms_c, 3), "completed": round(ms_n, 3) if ms_n else None},
+    }
+    if meta:
+        out["training"] = {k: meta[k] for k in ("fit_phantoms", "validation_phantoms", "scatterers", "epochs",
+                                                "bins_per_phantom", "batch", "seconds", "validation")}
+        out["training"]["final_loss"] = meta["history"][-1] if meta.get("history") else None
+    return out
+
+
+def study_report(np):
+    """Scheme / compounding image metrics on synthetic phantoms (gCNR of an anechoic cyst, lateral
+    FWHM of point targets) against DAS on the same data, N = 15 and N = 7."""
+    from paper_2603_22496_amd import study as ST
+    rep = ST.run(log=lambda s: print("bench: " + s, file=sys.stderr, flush=True))
+    out = {"geometry": rep["geometry"], "results": {}}
+    for n, res in rep["results"].items():
+        out["results"][n] = {name: {"compression": r["compression"], "gcnr": r["gcnr"],
+                                    "fwhm_mm_mean": round(float(np.nanmean(r["fwhm_mm"])), 3)}
+                             for name, r in res.items()}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -346,6 +423,14 @@ def main():
 
     if not args.no_ensemble:
         res["ensemble"] = ensemble_report(kk, C, torch, np, args)
+
+    if not args.no_completion:
+        res["completion"] = completion_report(kk, C, torch, np, args)
+        print("bench: completion %s" % json.dumps(res["completion"]["rel_l2_vs_fully_sampled_gpu"]), file=sys.stderr,
+              flush=True)
+
+    if not args.no_study:
+        res["study"] = study_report(np)
 
     if args.copy_mb > 0:
         src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
@@ -432,6 +517,10 @@ def main():
         out["precision_large"] = res["precision"]
     if "ensemble" in res:
         out["ensemble"] = res["ensemble"]
+    if "completion" in res:
+        out["completion"] = res["completion"]
+    if "study" in res:
+        out["study"] = res["study"]
     if "das_ms" in res:
         das_units = w.X * w.Z * w.N * w.L                 # pixel x (transmit, element) gathers
         out["stage_rooflines"]["das"] = {

@@ -447,6 +447,8 @@ int32_t kk_spectrum_inverse(const float* spec, int32_t ntraces, int32_t tpad, in
  * Parameters (FP32, kk_net_param_count of them): per layer l the weights W[9][32][cin]
  * (tap t = 3 (dy+1) + (dx+1), output channel, input channel; cin = KK_NET_IN for l = 0,
  * KK_NET_WIDTH after) then the bias [32]; the last layer's output channels 2..31 must be zero.
+ * Layer l reads its input at (h + dy eh_l, w + dx ew_l): `dilation` is a host array
+ * [KK_NET_LAYERS][2] = (eh_l, ew_l), 1..64, or NULL for all 1.
  * Limits: 16 <= W <= 192 with W a multiple of 16; H >= 1; B >= 1.
  * ===================================================================================== */
 #define KK_NET_LAYERS 6
@@ -478,10 +480,11 @@ int32_t kk_net_prepare(const float* spec, int32_t H, int32_t Msrc, int32_t kpad,
                        float* scale, void* stream);
 
 /* kk_net_forward (device) - out = network(grid); batch row b reads grid sample sidx[b] (dev,
- * or b when sidx is NULL).  ws: kk_net_workspace_bytes(B, H, W).
+ * or b when sidx is NULL).  ws: kk_net_workspace_bytes(B, H, W).  dilation as above.
  * Errors: KK_E_NULL, KK_E_ARG (shape), KK_E_WORKSPACE, KK_E_HIP. */
 int32_t kk_net_forward(const void* state, const uint16_t* grid, const int32_t* sidx, int32_t B,
-                       int32_t H, int32_t W, float* out, void* ws, size_t ws_bytes, void* stream);
+                       int32_t H, int32_t W, const int32_t* dilation, float* out, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* kk_net_backward (device) - forward pass, loss and parameter gradient of a batch:
  *   loss (dev float) = inv_count * sum over unobserved pairs of |out - target|^2
@@ -491,12 +494,12 @@ int32_t kk_net_forward(const void* state, const uint16_t* grid, const int32_t* s
  * weights.  kk_net_train_step = kk_net_backward + kk_net_adam.
  * Errors: KK_E_NULL, KK_E_ARG, KK_E_WORKSPACE, KK_E_HIP. */
 int32_t kk_net_backward(void* state, const uint16_t* grid, const float* target, const int32_t* sidx,
-                        int32_t B, int32_t H, int32_t W, float inv_count, float* loss, void* ws,
-                        size_t ws_bytes, void* stream);
+                        int32_t B, int32_t H, int32_t W, const int32_t* dilation, float inv_count,
+                        float* loss, void* ws, size_t ws_bytes, void* stream);
 int32_t kk_net_adam(void* state, int32_t step, float lr, void* stream);
 int32_t kk_net_train_step(void* state, const uint16_t* grid, const float* target, const int32_t* sidx,
-                          int32_t B, int32_t H, int32_t W, float inv_count, int32_t step, float lr,
-                          float* loss, void* ws, size_t ws_bytes, void* stream);
+                          int32_t B, int32_t H, int32_t W, const int32_t* dilation, float inv_count,
+                          int32_t step, float lr, float* loss, void* ws, size_t ws_bytes, void* stream);
 
 /* kk_net_merge (device) - completed spectrum of B bins: dst[h][w][k] = spec[h][obs_src[j]][k]
  * where column w is observed (j = grid_to_obs[w] >= 0), else out[b][h][w] * scale[b]; dst dev

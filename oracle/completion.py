@@ -14,8 +14,9 @@ transmit angle, w the receive angle of the bank, c the channel.
   sample input   c = 0, 1: Re, Im of the observed pairs divided by the bin's scale, 0 where
                  unobserved; c = 2: 1 where observed.  scale = root mean square of the
                  observed pairs' moduli.  Target: Re, Im of the full grid / scale.
-  conv3x3        y[b][h][w][o] = bias[o] + sum_{t, c} W[t][o][c] x[b][h+dy][w+dx][c], with
-                 t = 3 (dy + 1) + (dx + 1), dy, dx in {-1, 0, 1}, x = 0 outside the grid
+  conv3x3        y[b][h][w][o] = bias[o] + sum_{t, c} W[t][o][c] x[b][h+dy*eh][w+dx*ew][c], with
+                 t = 3 (dy + 1) + (dx + 1), dy, dx in {-1, 0, 1}, dilation (eh, ew) >= 1,
+                 x = 0 outside the grid
   network        a_0 = input; a_l = relu(conv_l(a_{l-1})), l = 1..L-1; out = conv_L(a_{L-1})
   loss           mean over unobserved positions and both components of (out - target)^2
   completion     observed pairs keep their values; unobserved take out * scale
@@ -39,35 +40,38 @@ def _shifted(x: np.ndarray, dy: int, dx: int) -> np.ndarray:
     return out
 
 
-def conv3x3(x: np.ndarray, W: np.ndarray, bias: np.ndarray) -> np.ndarray:
-    """x [B][H][W][Ci], W [9][Co][Ci], bias [Co] -> y [B][H][W][Co] (FP64)."""
+def conv3x3(x: np.ndarray, W: np.ndarray, bias: np.ndarray, dil=(1, 1)) -> np.ndarray:
+    """x [B][H][W][Ci], W [9][Co][Ci], bias [Co], dilation (eh, ew) -> y [B][H][W][Co] (FP64)."""
     x = np.asarray(x, dtype=np.float64)
     y = np.zeros(x.shape[:3] + (W.shape[1],), dtype=np.float64)
     for t, (dy, dx) in enumerate(TAPS):
-        y += _shifted(x, dy, dx) @ np.asarray(W[t], dtype=np.float64).T
+        y += _shifted(x, dy * dil[0], dx * dil[1]) @ np.asarray(W[t], dtype=np.float64).T
     return y + np.asarray(bias, dtype=np.float64)
 
 
-def conv3x3_backward(x: np.ndarray, W: np.ndarray, gy: np.ndarray):
-    """Gradients of sum(gy * conv3x3(x, W, b)): (gx [B][H][W][Ci], gW [9][Co][Ci], gb [Co])."""
+def conv3x3_backward(x: np.ndarray, W: np.ndarray, gy: np.ndarray, dil=(1, 1)):
+    """Gradients of sum(gy * conv3x3(x, W, b, dil)): (gx [B][H][W][Ci], gW [9][Co][Ci], gb [Co])."""
     x = np.asarray(x, dtype=np.float64)
     gy = np.asarray(gy, dtype=np.float64)
     gW = np.zeros(W.shape, dtype=np.float64)
     gx = np.zeros(x.shape, dtype=np.float64)
     for t, (dy, dx) in enumerate(TAPS):
-        xs = _shifted(x, dy, dx)
+        sy, sx = dy * dil[0], dx * dil[1]
+        xs = _shifted(x, sy, sx)
         gW[t] = np.einsum("bhwo,bhwc->oc", gy, xs)
-        # y[h][w] took x[h+dy][w+dx]: its gradient flows back to that position
-        gx += _shifted(gy @ np.asarray(W[t], dtype=np.float64), -dy, -dx)
+        # y[h][w] took x[h+sy][w+sx]: its gradient flows back to that position
+        gx += _shifted(gy @ np.asarray(W[t], dtype=np.float64), -sy, -sx)
     return gx, gW, gy.sum(axis=(0, 1, 2))
 
 
-def forward(x: np.ndarray, params):
-    """params: list of (W, bias) per layer.  Returns (out, activations a_0..a_{L-1})."""
+def forward(x: np.ndarray, params, dils=None):
+    """params: list of (W, bias) per layer, dils: (eh, ew) per layer (default 1).  Returns
+    (out, activations a_0..a_{L-1})."""
+    dils = dils or [(1, 1)] * len(params)
     acts = [np.asarray(x, dtype=np.float64)]
     a = acts[0]
     for l, (W, b) in enumerate(params):
-        z = conv3x3(a, W, b)
+        z = conv3x3(a, W, b, dils[l])
         if l < len(params) - 1:
             a = np.maximum(z, 0.0)
             acts.append(a)
@@ -76,15 +80,16 @@ def forward(x: np.ndarray, params):
     raise ValueError("empty network")
 
 
-def backward(params, acts, gout):
+def backward(params, acts, gout, dils=None):
     """Gradients [(gW, gb)] per layer of sum(gout * out), from forward's activations."""
+    dils = dils or [(1, 1)] * len(params)
     grads = [None] * len(params)
     g = np.asarray(gout, dtype=np.float64)
     for l in range(len(params) - 1, -1, -1):
         W, _ = params[l]
         if l < len(params) - 1:
             g = g * (acts[l + 1] > 0)          # relu: a_{l+1} = relu(z_{l+1}) > 0 exactly where z > 0
-        gx, gW, gb = conv3x3_backward(acts[l], W, g)
+        gx, gW, gb = conv3x3_backward(acts[l], W, g, dils[l])
         grads[l] = (gW, gb)
         g = gx
     return grads

@@ -7,8 +7,8 @@
 // pairs scaled by 1/scale (scale = root mean square of the observed pairs) in c = 0, 1 and the
 // observation mask in c = 2 (c = 3..7 zero); the network predicts the unobserved pairs.
 //
-//   conv3x3   y[b][h][w][o] = bias[o] + sum_{t,c} W[t][o][c] x[b][h+dy][w+dx][c], t = 3(dy+1) +
-//             (dx+1), zero outside the grid.  One wave = 32 grid positions of one row x 32
+//   conv3x3   y[b][h][w][o] = bias[o] + sum_{t,c} W[t][o][c] x[b][h+dy*eh][w+dx*ew][c], t = 3(dy+1)
+//             + (dx+1), dilation (eh, ew) per layer, zero outside the grid.  One wave = 32 grid positions of one row x 32
 //             output channels: A = weights (rows = output channels, K = 16 (tap, channel)
 //             pairs), B = input patch (K x 32 positions), 18 MFMAs for 32 input channels.
 //   backward  input gradient = the same convolution of the output gradient with the
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(const uint16_t* __restrict
                                                       const uint16_t* __restrict__ mask,
                                                       const uint16_t* __restrict__ wk,
                                                       const float* __restrict__ bias, void* __restrict__ out, int B,
-                                                      int H, int W) {
+                                                      int H, int W, int dh, int dw) {
     static_assert(CIN == 8 || CIN == 32, "input channels");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wtiles = (W + 31) >> 5;
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(const uint16_t* __restrict
         u32x4 a = {0u, 0u, 0u, 0u}, x = {0u, 0u, 0u, 0u};
         if (tap < kTaps) {
             a = *reinterpret_cast<const u32x4*>(wk + ((size_t)tap * kWidth + col) * CIN + ci0);
-            const int hh = h + tap / 3 - 1, ww = w + tap % 3 - 1;
+            const int hh = h + (tap / 3 - 1) * dh, ww = w + (tap % 3 - 1) * dw;
             if (hh >= 0 && hh < H && ww >= 0 && ww < W) {
                 x = *reinterpret_cast<const u32x4*>(in + (((size_t)bs * H + hh) * W + ww) * CIN + ci0);
                 if constexpr ((FLAGS & kMaskIn) != 0) {
@@ -165,7 +165,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(const uint16_t* __restrict
 template <int CIN>
 __global__ __launch_bounds__(192) void wgrad_kernel(const uint16_t* __restrict__ gout, const uint16_t* __restrict__ mask,
                                                     const uint16_t* __restrict__ xin, const int32_t* __restrict__ sidx,
-                                                    float* __restrict__ part, int B, int H, int W, int rows_per_block) {
+                                                    float* __restrict__ part, int B, int H, int W, int rows_per_block,
+                                                    int dh, int dw) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[(kWidth + 9 * CIN) * (kMaxGridW + 8)];
     const int stride = W + 8;                     // BF16 elements per LDS row (16-byte pad)
     uint16_t* zT = smem;                          // [32][stride]: gradient, channel-major
@@ -209,18 +210,18 @@ __global__ __launch_bounds__(192) void wgrad_kernel(const uint16_t* __restrict__
                 *reinterpret_cast<uint32_t*>(zT + (cg + j) * stride + w) = e0 | (e1 << 16);
             }
         }
-        // input rows h-1, h, h+1, each stored three times shifted by dx = -1, 0, 1:
-        // xT[dx+1][dy+1][c][w] = x[h+dy][w+dx][c] (zero outside the grid)
+        // input rows h + dy eh (dy = -1, 0, 1), each stored three times shifted by dx ew:
+        // xT[dx+1][dy+1][c][w] = x[h+dy*eh][w+dx*ew][c] (zero outside the grid)
         for (int it = tid; it < 9 * (W / 2) * (CIN / 8); it += 192) {
             const int cgi = it % (CIN / 8);
             const int rest = it / (CIN / 8);
             const int w = 2 * (rest % (W / 2));
             const int sh = rest / (W / 2);  // 0..8 = (dx+1) * 3 + (dy+1)
             const int dxi = sh / 3, dyi = sh - (sh / 3) * 3;
-            const int hh = h + dyi - 1;
+            const int hh = h + (dyi - 1) * dh;
             u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
             if (hh >= 0 && hh < H) {
-                const int w0 = w + dxi - 1, w1 = w0 + 1;
+                const int w0 = w + (dxi - 1) * dw, w1 = w0 + 1;
                 const size_t rowp = ((size_t)bs * H + hh) * W;
                 if (w0 >= 0 && w0 < W) v0 = *reinterpret_cast<const u32x4*>(xin + (rowp + w0) * CIN + cgi * 8);
                 if (w1 >= 0 && w1 < W) v1 = *reinterpret_cast<const u32x4*>(xin + (rowp + w1) * CIN + cgi * 8);
@@ -454,22 +455,31 @@ bool net_ws(int B, int H, int W, NetWs* w) {
 }
 
 
+// per-layer dilations (eh, ew) from the caller's array, or all 1; false when out of range
+bool read_dilation(const int32_t* d, int* out) {
+    for (int i = 0; i < 2 * kLayers; ++i) {
+        out[i] = d ? d[i] : 1;
+        if (out[i] < 1 || out[i] > 64) return false;
+    }
+    return true;
+}
+
 hipError_t conv(int l, int flags, const uint16_t* in, const int32_t* sidx, const uint16_t* mask, const uint16_t* wk,
-                const float* bias, void* out, int B, int H, int W, hipStream_t st) {
+                const float* bias, void* out, int B, int H, int W, int dh, int dw, hipStream_t st) {
     const int64_t tiles = (int64_t)B * H * ((W + 31) / 32);
     const dim3 g((unsigned)((tiles + 3) / 4)), blk(256);
     if (l == 0) {
-        hipLaunchKernelGGL((conv3x3_kernel<kIn, kRelu | kBias>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H, W);
+        hipLaunchKernelGGL((conv3x3_kernel<kIn, kRelu | kBias>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H, W, dh, dw);
     } else if (flags == (kRelu | kBias)) {
         hipLaunchKernelGGL((conv3x3_kernel<kWidth, kRelu | kBias>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H,
-                           W);
+                           W, dh, dw);
     } else if (flags == (kBias | kOutF32x2)) {
         hipLaunchKernelGGL((conv3x3_kernel<kWidth, kBias | kOutF32x2>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B,
-                           H, W);
+                           H, W, dh, dw);
     } else if (flags == kMaskIn) {
-        hipLaunchKernelGGL((conv3x3_kernel<kWidth, kMaskIn>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H, W);
+        hipLaunchKernelGGL((conv3x3_kernel<kWidth, kMaskIn>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H, W, dh, dw);
     } else if (flags == 0) {
-        hipLaunchKernelGGL((conv3x3_kernel<kWidth, 0>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H, W);
+        hipLaunchKernelGGL((conv3x3_kernel<kWidth, 0>), g, blk, 0, st, in, sidx, mask, wk, bias, out, B, H, W, dh, dw);
     } else {
         return hipErrorInvalidValue;
     }
@@ -477,7 +487,7 @@ hipError_t conv(int l, int flags, const uint16_t* in, const int32_t* sidx, const
 }
 
 hipError_t forward(const unsigned char* state, const uint16_t* grid, const int32_t* sidx, int B, int H, int W,
-                   unsigned char* ws, const NetWs& w, float* out, hipStream_t st) {
+                   const int* dil, unsigned char* ws, const NetWs& w, float* out, hipStream_t st) {
     const float* params = reinterpret_cast<const float*>(state + kStateParams);
     const uint16_t* wk = reinterpret_cast<const uint16_t*>(state + kStateW);
     const size_t a = align256(act_bytes(B, H, W));
@@ -487,10 +497,12 @@ hipError_t forward(const unsigned char* state, const uint16_t* grid, const int32
         hipError_t e;
         if (l < kLayers - 1) {
             uint16_t* y = reinterpret_cast<uint16_t*>(ws + w.act + l * a);
-            e = conv(l, kRelu | kBias, x, l == 0 ? sidx : nullptr, nullptr, wk + layer_koff(l), bias, y, B, H, W, st);
+            e = conv(l, kRelu | kBias, x, l == 0 ? sidx : nullptr, nullptr, wk + layer_koff(l), bias, y, B, H, W,
+                     dil[2 * l], dil[2 * l + 1], st);
             x = y;
         } else {
-            e = conv(l, kBias | kOutF32x2, x, nullptr, nullptr, wk + layer_koff(l), bias, out, B, H, W, st);
+            e = conv(l, kBias | kOutF32x2, x, nullptr, nullptr, wk + layer_koff(l), bias, out, B, H, W, dil[2 * l],
+                     dil[2 * l + 1], st);
         }
         if (e != hipSuccess) return e;
     }
@@ -498,13 +510,13 @@ hipError_t forward(const unsigned char* state, const uint16_t* grid, const int32
 }
 
 hipError_t wgrad(int l, const uint16_t* g, const uint16_t* mask, const uint16_t* x, const int32_t* sidx, float* part,
-                 float* dst, int B, int H, int W, const NetWs& w, hipStream_t st) {
+                 float* dst, int B, int H, int W, int dh, int dw, const NetWs& w, hipStream_t st) {
     if (layer_cin(l) == kIn)
         hipLaunchKernelGGL(wgrad_kernel<kIn>, dim3(w.wg_blocks), dim3(192), 0, st, g, mask, x, sidx, part, B, H, W,
-                           w.rows_per_block);
+                           w.rows_per_block, dh, dw);
     else
         hipLaunchKernelGGL(wgrad_kernel<kWidth>, dim3(w.wg_blocks), dim3(192), 0, st, g, mask, x, sidx, part, B, H,
-                           W, w.rows_per_block);
+                           W, w.rows_per_block, dh, dw);
     const int n = layer_wsize(l) + kWidth;
     hipLaunchKernelGGL(sum_parts_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, w.wg_blocks, n, dst);
     return hipGetLastError();
@@ -556,24 +568,27 @@ int32_t kk_net_prepare(const float* spec, int32_t H, int32_t Msrc, int32_t kpad,
 }
 
 int32_t kk_net_forward(const void* state, const uint16_t* grid, const int32_t* sidx, int32_t B, int32_t H, int32_t W,
-                       float* out, void* ws, size_t ws_bytes, void* stream) {
+                       const int32_t* dilation, float* out, void* ws, size_t ws_bytes, void* stream) {
     using namespace kk;
     if (!state || !grid || !out || !ws) return KK_E_NULL;
     NetWs w;
-    if (!net_ws(B, H, W, &w)) return KK_E_ARG;
+    int dil[2 * kLayers];
+    if (!net_ws(B, H, W, &w) || !read_dilation(dilation, dil)) return KK_E_ARG;
     if (ws_bytes < w.total) return KK_E_WORKSPACE;
-    return forward(static_cast<const unsigned char*>(state), grid, sidx, B, H, W, static_cast<unsigned char*>(ws), w,
-                   out, (hipStream_t)stream) == hipSuccess
+    return forward(static_cast<const unsigned char*>(state), grid, sidx, B, H, W, dil, static_cast<unsigned char*>(ws),
+                   w, out, (hipStream_t)stream) == hipSuccess
                ? KK_OK
                : KK_E_HIP;
 }
 
 int32_t kk_net_backward(void* state, const uint16_t* grid, const float* target, const int32_t* sidx, int32_t B,
-                        int32_t H, int32_t W, float inv_count, float* loss, void* ws, size_t ws_bytes, void* stream) {
+                        int32_t H, int32_t W, const int32_t* dilation, float inv_count, float* loss, void* ws,
+                        size_t ws_bytes, void* stream) {
     using namespace kk;
     if (!state || !grid || !target || !loss || !ws) return KK_E_NULL;
     NetWs w;
-    if (!net_ws(B, H, W, &w)) return KK_E_ARG;
+    int dil[2 * kLayers];
+    if (!net_ws(B, H, W, &w) || !read_dilation(dilation, dil)) return KK_E_ARG;
     if (!(inv_count > 0.f)) return KK_E_ARG;
     if (ws_bytes < w.total) return KK_E_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
@@ -586,7 +601,7 @@ int32_t kk_net_backward(void* state, const uint16_t* grid, const float* target, 
     auto act = [&](int l) -> const uint16_t* {  // output of layer l (0-based), l < kLayers - 1
         return reinterpret_cast<const uint16_t*>(wsb + w.act + l * a);
     };
-    if (forward(s, grid, sidx, B, H, W, wsb, w, out, st) != hipSuccess) return KK_E_HIP;
+    if (forward(s, grid, sidx, B, H, W, dil, wsb, w, out, st) != hipSuccess) return KK_E_HIP;
     const int HW = H * W;
     const int lblocks = (int)(((int64_t)B * HW + 255) / 256);
     uint16_t* g[2] = {reinterpret_cast<uint16_t*>(wsb + w.g0), reinterpret_cast<uint16_t*>(wsb + w.g1)};
@@ -601,12 +616,15 @@ int32_t kk_net_backward(void* state, const uint16_t* grid, const float* target, 
         // g[cur]: gradient at layer l's output (before its ReLU derivative)
         const uint16_t* mask = l < kLayers - 1 ? act(l) : nullptr;
         const uint16_t* x = l > 0 ? act(l - 1) : grid;
-        if (wgrad(l, g[cur], mask, x, l > 0 ? nullptr : sidx, part, grad + layer_poff(l), B, H, W, w, st) !=
+        const int dh = dil[2 * l], dw = dil[2 * l + 1];
+        if (wgrad(l, g[cur], mask, x, l > 0 ? nullptr : sidx, part, grad + layer_poff(l), B, H, W, dh, dw, w, st) !=
             hipSuccess)
             return KK_E_HIP;
         if (l > 0) {
+            // the input gradient is the convolution with the flipped, transposed weights at the
+            // same dilation
             if (conv(l, mask ? kMaskIn : 0, g[cur], nullptr, mask, wk + layer_toff(l), nullptr, g[1 - cur], B, H, W,
-                     st) != hipSuccess)
+                     dh, dw, st) != hipSuccess)
                 return KK_E_HIP;
             cur = 1 - cur;
         }
@@ -632,10 +650,11 @@ int32_t kk_net_adam(void* state, int32_t step, float lr, void* stream) {
 }
 
 int32_t kk_net_train_step(void* state, const uint16_t* grid, const float* target, const int32_t* sidx, int32_t B,
-                          int32_t H, int32_t W, float inv_count, int32_t step, float lr, float* loss, void* ws,
-                          size_t ws_bytes, void* stream) {
+                          int32_t H, int32_t W, const int32_t* dilation, float inv_count, int32_t step, float lr,
+                          float* loss, void* ws, size_t ws_bytes, void* stream) {
     if (step < 1 || !(lr > 0.f)) return KK_E_ARG;
-    const int32_t rc = kk_net_backward(state, grid, target, sidx, B, H, W, inv_count, loss, ws, ws_bytes, stream);
+    const int32_t rc =
+        kk_net_backward(state, grid, target, sidx, B, H, W, dilation, inv_count, loss, ws, ws_bytes, stream);
     return rc != KK_OK ? rc : kk_net_adam(state, step, lr, stream);
 }
 

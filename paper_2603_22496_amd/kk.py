@@ -138,11 +138,11 @@ def lib():
             "kk_net_load": [_vp, _vp, _vp],
             "kk_net_read": [_vp, _i32, _vp, _vp],
             "kk_net_prepare": [_vp, _i32, _i32, _i32, _vp, _i32, _i32, _vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp],
-            "kk_net_forward": [_vp, _vp, _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp],
-            "kk_net_backward": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, ctypes.c_float, _vp, _vp, _sz, _vp],
+            "kk_net_forward": [_vp, _vp, _vp, _i32, _i32, _i32, _i32p, _vp, _vp, _sz, _vp],
+            "kk_net_backward": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32p, ctypes.c_float, _vp, _vp, _sz, _vp],
             "kk_net_adam": [_vp, _i32, ctypes.c_float, _vp],
-            "kk_net_train_step": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, ctypes.c_float, _i32, ctypes.c_float, _vp,
-                                  _vp, _sz, _vp],
+            "kk_net_train_step": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32p, ctypes.c_float, _i32, ctypes.c_float,
+                                  _vp, _vp, _sz, _vp],
             "kk_net_merge": [_vp, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp],
             "kk_clear": [_vp, _sz, _vp],
             "kk_ensemble_autotune": [ctypes.POINTER(EnsembleFrame), _i32, _i32, ctypes.c_int64, _vp, _sz, _vp, _vp,
@@ -412,8 +412,10 @@ class Net:
     """Device state of the completion network (parameters, Adam moments, gradient, BF16
     weights) and its workspace for batches of up to B grids of H x W."""
 
-    def __init__(self, params: np.ndarray, B: int, H: int, W: int, device="cuda"):
+    def __init__(self, params: np.ndarray, B: int, H: int, W: int, device="cuda", dilation=None):
         self.B, self.H, self.W = B, H, W
+        self.dilation = [(1, 1)] * NET_LAYERS if dilation is None else [tuple(d) for d in dilation]
+        self._dil = np.ascontiguousarray(np.array(self.dilation, dtype=np.int32).ravel())
         self.state = torch.zeros(int(lib().kk_net_state_bytes()), dtype=torch.uint8, device=device)
         nb = int(lib().kk_net_workspace_bytes(B, H, W))
         if nb == 0:
@@ -438,16 +440,16 @@ class Net:
     def forward(self, grid, out, B=None, sidx=None, stream=None):
         B = self.B if B is None else B
         _check("kk_net_forward", lib().kk_net_forward(_dev(self.state), _dev(grid), _dev(sidx) if sidx is not None
-                                                      else None, B, self.H, self.W, _dev(out), _dev(self.ws),
-                                                      self.ws.numel(), _stream(stream)))
+                                                      else None, B, self.H, self.W, _ip(self._dil), _dev(out),
+                                                      _dev(self.ws), self.ws.numel(), _stream(stream)))
         return out
 
     def backward(self, grid, target, inv_count: float, B=None, sidx=None, stream=None):
         B = self.B if B is None else B
         _check("kk_net_backward", lib().kk_net_backward(_dev(self.state), _dev(grid), _dev(target),
                                                         _dev(sidx) if sidx is not None else None, B, self.H, self.W,
-                                                        inv_count, _dev(self.loss), _dev(self.ws), self.ws.numel(),
-                                                        _stream(stream)))
+                                                        _ip(self._dil), inv_count, _dev(self.loss), _dev(self.ws),
+                                                        self.ws.numel(), _stream(stream)))
         return self.loss
 
     def adam(self, lr: float, stream=None):
@@ -459,8 +461,9 @@ class Net:
         self.step += 1
         _check("kk_net_train_step", lib().kk_net_train_step(_dev(self.state), _dev(grid), _dev(target),
                                                             _dev(sidx) if sidx is not None else None, B, self.H,
-                                                            self.W, inv_count, self.step, lr, _dev(self.loss),
-                                                            _dev(self.ws), self.ws.numel(), _stream(stream)))
+                                                            self.W, _ip(self._dil), inv_count, self.step, lr,
+                                                            _dev(self.loss), _dev(self.ws), self.ws.numel(),
+                                                            _stream(stream)))
         return self.loss
 
 

@@ -77,11 +77,15 @@ def _to_bf16_dev(K, a):
     return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).cuda()
 
 
-def _emulated_forward(layers, x):
+DILATED = [(1, 1), (1, 2), (2, 4), (2, 8), (4, 16), (1, 1)]
+
+
+def _emulated_forward(layers, x, dils=None):
+    dils = dils or [(1, 1)] * len(layers)
     acts = [x]
     a = x
     for l, (W, b) in enumerate(layers):
-        z = OC.conv3x3(a, W, b)
+        z = OC.conv3x3(a, W, b, dils[l])
         if l < len(layers) - 1:
             a = bf16(np.maximum(z, 0.0))
             acts.append(a)
@@ -89,30 +93,32 @@ def _emulated_forward(layers, x):
             return z, acts
 
 
-def _emulated_backward(layers, acts, gout):
+def _emulated_backward(layers, acts, gout, dils=None):
+    dils = dils or [(1, 1)] * len(layers)
     grads = [None] * len(layers)
     g = gout
     for l in range(len(layers) - 1, -1, -1):
         if l < len(layers) - 1:
             g = g * (acts[l + 1] > 0)
-        gx, gW, gb = OC.conv3x3_backward(acts[l], layers[l][0], g)
+        gx, gW, gb = OC.conv3x3_backward(acts[l], layers[l][0], g, dils[l])
         grads[l] = (gW, gb)
         g = bf16(gx)
     return grads
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 5, 32), (1, 31, 128), (3, 7, 48)])
-def test_forward_matches_oracle(kk, B, H, W):
+@pytest.mark.parametrize("B,H,W,dils", [(2, 5, 32, None), (1, 31, 128, None), (3, 7, 48, None),
+                                         (2, 31, 128, DILATED), (1, 9, 64, DILATED)])
+def test_forward_matches_oracle(kk, B, H, W, dils):
     import torch
-    print("net forward B %d H %d W %d" % (B, H, W), flush=True)
+    print("net forward B %d H %d W %d dilated %s" % (B, H, W, dils is not None), flush=True)
     p = _params(kk, 1)
     cols = sorted(np.random.default_rng(2).choice(W, size=max(2, W // 10), replace=False).tolist())
     x = _grid(3, B, H, W, cols)
-    net = kk.Net(p, B, H, W)
+    net = kk.Net(p, B, H, W, dilation=dils)
     out = torch.zeros((B, H, W, 2), dtype=torch.float32, device="cuda")
     net.forward(_to_bf16_dev(kk, x), out)
     torch.cuda.synchronize()
-    ref, _ = _emulated_forward(_unpack(kk, p), x)
+    ref, _ = _emulated_forward(_unpack(kk, p), x, dils)
     rel = _rel(out.cpu().numpy(), ref[..., :2])
     print("  rel-L2 %.3e" % rel, flush=True)
     assert rel <= 5e-3, rel
@@ -133,10 +139,10 @@ def test_forward_sample_index(kk):
     assert _rel(out.cpu().numpy(), ref[..., :2]) <= 5e-3
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 5, 32), (2, 31, 128)])
-def test_gradients_match_oracle(kk, B, H, W):
+@pytest.mark.parametrize("B,H,W,dils", [(2, 5, 32, None), (2, 31, 128, None), (2, 31, 128, DILATED)])
+def test_gradients_match_oracle(kk, B, H, W, dils):
     import torch
-    print("net gradients B %d H %d W %d" % (B, H, W), flush=True)
+    print("net gradients B %d H %d W %d dilated %s" % (B, H, W, dils is not None), flush=True)
     p = _params(kk, 6)
     cols = list(range(0, W, 7))
     x = _grid(7, B, H, W, cols)
@@ -144,17 +150,17 @@ def test_gradients_match_oracle(kk, B, H, W):
     obs = x[..., 2]
     n_un = float((1 - obs).sum())
     inv = 1.0 / (2 * n_un)
-    net = kk.Net(p, B, H, W)
+    net = kk.Net(p, B, H, W, dilation=dils)
     loss = net.backward(_to_bf16_dev(kk, x), torch.from_numpy(tgt.astype(np.float32)).cuda(), inv)
     torch.cuda.synchronize()
     g_gpu = net.read(kk.NET_GRADS)
     layers = _unpack(kk, p)
-    out, acts = _emulated_forward(layers, x)
+    out, acts = _emulated_forward(layers, x, dils)
     l_ref, gout = OC.masked_mse(out[..., :2], tgt, obs)
     assert abs(float(loss.item()) - l_ref) <= 1e-2 * l_ref
     g32 = np.zeros(out.shape)
     g32[..., :2] = bf16(gout)
-    grads = _emulated_backward(layers, acts, g32)
+    grads = _emulated_backward(layers, acts, g32, dils)
     for l, (cin, wo, bo) in enumerate(kk.net_layer_shapes()):
         gW, gb = grads[l]
         rw = _rel(g_gpu[wo:bo].reshape(9, 32, cin), gW)
@@ -163,11 +169,11 @@ def test_gradients_match_oracle(kk, B, H, W):
         assert rw <= 3e-2 and rb <= 3e-2, (l, rw, rb)
     # and against the plain FP64 network gradient (FP32 weights, no BF16 anywhere): the same
     # gradient up to what BF16 weights and activations change through six layers
-    out64, acts64 = OC.forward(x, _unpack(kk, p, rounded=False))
+    out64, acts64 = OC.forward(x, _unpack(kk, p, rounded=False), dils)
     _, gout64 = OC.masked_mse(out64[..., :2], tgt, obs)
     g64 = np.zeros(out64.shape)
     g64[..., :2] = gout64
-    grads64 = OC.backward(_unpack(kk, p, rounded=False), acts64, g64)
+    grads64 = OC.backward(_unpack(kk, p, rounded=False), acts64, g64, dils)
     for l, (cin, wo, bo) in enumerate(kk.net_layer_shapes()):
         assert _rel(g_gpu[wo:bo].reshape(9, 32, cin), grads64[l][0]) <= 0.3
 
@@ -287,8 +293,74 @@ def test_net_errors(kk):
     assert L.kk_net_workspace_bytes(0, 5, 32) == 0
     assert L.kk_net_read(None, 0, None, None) == kk.KK_E_NULL
     assert L.kk_spectrum_bins(100) == 0 and L.kk_spectrum_bins(4096) == 2056
+    bad = kk.Net(_params(kk, 15), 2, 5, 32)
+    bad._dil[3] = 0
+    import torch
+    with pytest.raises(kk.KKError):
+        bad.forward(torch.zeros((2, 5, 32, 8), dtype=torch.bfloat16, device="cuda"),
+                    torch.zeros((2, 5, 32, 2), dtype=torch.float32, device="cuda"))
     net = kk.Net(_params(kk, 15), 2, 5, 32)
     buf = np.zeros(8, np.float32)
     assert L.kk_net_read(kk._dev(net.state), 9, buf.ctypes.data, None) == kk.KK_E_ARG
     assert L.kk_net_adam(kk._dev(net.state), 0, ctypes.c_float(1e-3), None) == kk.KK_E_ARG
     assert L.kk_clear(kk._dev(net.ws), 7, None) == kk.KK_E_ARG
+
+
+@pytest.fixture(scope="module")
+def pipeline(kk):
+    from paper_2603_22496_amd import completion as CP
+    cs = CP.setup()
+    return CP, cs, CP.Device(cs)
+
+
+def test_observed_spectrum_is_the_full_banks_columns(kk, pipeline):
+    import torch
+    CP, cs, d = pipeline
+    su = cs.full
+    rf = kk.to_device(CP.phantom(cs, 12000, 300).rf)
+    full = kk.decompose_spectrum(rf, su.geom, d.shift_full, len(su.sel["rx_theta"]), su.tpad, ws=d.ws)
+    obs = kk.decompose_spectrum(rf, su.geom, d.shift_obs, len(cs.cols), su.tpad, ws=d.ws)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(obs.cpu().numpy(), full.cpu().numpy()[:, cs.cols, :])
+
+
+def test_perfect_prediction_reproduces_the_full_image(kk, pipeline):
+    # completing every band bin (DC to 9.75 MHz) with the true grid leaves only the unobserved
+    # bins above the band and the Nyquist bin out of the fully sampled image
+    import torch
+    CP, cs, d = pipeline
+    su = cs.full
+    W = len(su.sel["rx_theta"])
+    rf = kk.to_device(CP.phantom(cs, 12001, 300).rf)
+    ref = CP.full_image(cs, d, rf).cpu().numpy()
+    full = kk.decompose_spectrum(rf, su.geom, d.shift_full, W, su.tpad, ws=d.ws)
+    obs = kk.decompose_spectrum(rf, su.geom, d.shift_obs, len(cs.cols), su.tpad, ws=d.ws)
+    tgt = torch.zeros((CP.BATCH, cs.w.N, W, 2), dtype=torch.float32, device="cuda")
+    kk.clear(d.out)
+    for k0 in range(0, cs.kpad, CP.BATCH):
+        B = min(CP.BATCH, cs.kpad - k0)
+        kk.net_merge(d.out, d.scale, obs, d.cols_obs, d.g2o, d.spec_done, k_first=k0, B=B)
+    for k0 in range(cs.k_lo, cs.k_hi, CP.BATCH):
+        B = min(CP.BATCH, cs.k_hi - k0)
+        kk.net_prepare(full, d.cols_full, d.g2o, d.grid, d.scale, k_first=k0, B=B, target=tgt)
+        kk.net_merge(tgt, d.scale, obs, d.cols_obs, d.g2o, d.spec_done, k_first=k0, B=B)
+    kk.spectrum_inverse(d.spec_done, su.tpad, cs.w.T, out=d.rt_full)
+    img = kk.beamform(d.rt_full, su.plan, d.plan_full, image=d.img, ws=d.bws).cpu().numpy()
+    rel = _rel(img, ref)
+    print("perfect completion rel-L2 %.3e" % rel, flush=True)
+    assert rel <= 1e-3
+
+
+def test_complete_image_paths_run(kk, pipeline):
+    import torch
+    CP, cs, d = pipeline
+    rf = kk.to_device(CP.phantom(cs, 12002, 300).rf)
+    ref = CP.full_image(cs, d, rf).cpu().numpy()
+    plain = CP.complete_image(cs, d, rf, None).cpu().numpy()
+    net = kk.Net(CP.init_params(0), CP.BATCH, cs.w.N, len(cs.full.sel["rx_theta"]))
+    done = CP.complete_image(cs, d, rf, net).cpu().numpy()
+    assert np.isfinite(plain).all() and np.isfinite(done).all()
+    e_plain = CP.scaled_error(plain, ref)
+    print("untrained: compressed rel-L2 %.3f (best gain %.3f), completed %.3f" % (e_plain[0], e_plain[1],
+                                                                                 CP.scaled_error(done, ref)[0]))
+    assert e_plain[1] < 1.0

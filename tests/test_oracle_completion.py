@@ -10,7 +10,7 @@ def _rng(seed=0):
     return np.random.default_rng(seed)
 
 
-def _brute_conv(x, W, b):
+def _brute_conv(x, W, b, dil=(1, 1)):
     """Seven nested loops over the definition, on tiny grids."""
     B, H, Wd, Ci = x.shape
     Co = W.shape[1]
@@ -22,7 +22,7 @@ def _brute_conv(x, W, b):
                     s = b[o]
                     for dy in (-1, 0, 1):
                         for dx in (-1, 0, 1):
-                            hh, ww = h + dy, w + dx
+                            hh, ww = h + dy * dil[0], w + dx * dil[1]
                             if 0 <= hh < H and 0 <= ww < Wd:
                                 t = 3 * (dy + 1) + (dx + 1)
                                 for c in range(Ci):
@@ -31,12 +31,24 @@ def _brute_conv(x, W, b):
     return y
 
 
-def test_conv_matches_brute_force():
+@pytest.mark.parametrize("dil", [(1, 1), (2, 3), (1, 4)])
+def test_conv_matches_brute_force(dil):
     r = _rng(1)
-    x = r.standard_normal((2, 3, 5, 2))
+    x = r.standard_normal((2, 5, 9, 2))
     W = r.standard_normal((9, 3, 2))
     b = r.standard_normal(3)
-    np.testing.assert_allclose(OC.conv3x3(x, W, b), _brute_conv(x, W, b), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(OC.conv3x3(x, W, b, dil), _brute_conv(x, W, b, dil), rtol=0, atol=1e-12)
+
+
+def test_dilated_delta_kernel_is_a_long_shift():
+    r = _rng(9)
+    x = r.standard_normal((1, 6, 11, 1))
+    W = np.zeros((9, 1, 1))
+    W[3 * 2 + 0] = 1.0                       # dy = +1, dx = -1
+    y = OC.conv3x3(x, W, np.zeros(1), (2, 3))
+    ref = np.zeros_like(x)
+    ref[0, :4, 3:, 0] = x[0, 2:, :8, 0]      # y[h][w] = x[h + 2][w - 3]
+    np.testing.assert_array_equal(y, ref)
 
 
 @pytest.mark.parametrize("dy,dx", [(0, 0), (-1, 0), (1, 1), (0, -1), (1, -1)])
@@ -71,20 +83,21 @@ def _params(r, widths):
             for ci, co in zip(widths[:-1], widths[1:])]
 
 
-def test_network_gradients_match_finite_differences():
+@pytest.mark.parametrize("dils", [None, [(1, 2), (2, 1), (1, 3)]])
+def test_network_gradients_match_finite_differences(dils):
     r = _rng(4)
     params = _params(r, [3, 4, 4, 2])
-    x = r.standard_normal((2, 3, 5, 3))
-    tgt = r.standard_normal((2, 3, 5, 2))
-    obs = (r.random((2, 3, 5)) < 0.3).astype(float)
+    x = r.standard_normal((2, 4, 7, 3))
+    tgt = r.standard_normal((2, 4, 7, 2))
+    obs = (r.random((2, 4, 7)) < 0.3).astype(float)
 
     def loss_of(ps, xx):
-        out, _ = OC.forward(xx, ps)
+        out, _ = OC.forward(xx, ps, dils)
         return OC.masked_mse(out, tgt, obs)[0]
 
-    out, acts = OC.forward(x, params)
+    out, acts = OC.forward(x, params, dils)
     _, gout = OC.masked_mse(out, tgt, obs)
-    grads = OC.backward(params, acts, gout)
+    grads = OC.backward(params, acts, gout, dils)
     h = 1e-6
     for l in range(len(params)):
         for which in (0, 1):
@@ -98,13 +111,14 @@ def test_network_gradients_match_finite_differences():
                 fd = (loss_of(ps_p, x) - loss_of(ps_m, x)) / (2 * h)
                 assert abs(fd - grads[l][which][idx]) <= 1e-6 * max(1.0, abs(fd)), (l, which, idx)
     # the input gradient (through every layer) by the conv backward
-    gx, _, _ = OC.conv3x3_backward(x, params[0][0], np.ones((2, 3, 5, 4)))
+    d0 = (dils or [(1, 1)])[0]
+    gx, _, _ = OC.conv3x3_backward(x, params[0][0], np.ones((2, 4, 7, 4)), d0)
     for _ in range(4):
         idx = tuple(int(r.integers(0, n)) for n in x.shape)
         xp, xm = x.copy(), x.copy()
         xp[idx] += h
         xm[idx] -= h
-        fd = (OC.conv3x3(xp, *params[0]).sum() - OC.conv3x3(xm, *params[0]).sum()) / (2 * h)
+        fd = (OC.conv3x3(xp, *params[0], d0).sum() - OC.conv3x3(xm, *params[0], d0).sum()) / (2 * h)
         assert abs(fd - gx[idx]) <= 1e-6 * max(1.0, abs(fd))
 
 
