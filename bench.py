@@ -85,18 +85,25 @@ def parse():
     return ap.parse_args()
 
 
-def timed(fn, steps, warmup, torch):
+def timed(fn, steps, warmup, torch, repeats=1):
+    """ms per call; with repeats > 1 the best of that many timed loops (a stage's steady state:
+    the first loop of back-to-back launches of one kernel in a process can run several times
+    slower than every later one)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        fn()
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps  # ms
+    best = None
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        best = ms if best is None else min(best, ms)
+    return best
 
 
 def precision_report(kk, C, torch, np, args):
@@ -405,8 +412,8 @@ def main():
     print("bench: %d KK frames in %.3fs wall, %.2f us/frame" % (args.steps, wall, ms * 1e3), file=sys.stderr,
           flush=True)
 
-    ms_dec = timed(decompose_only, args.steps, 5, torch)
-    ms_gather = timed(gather_only, args.steps, 5, torch)
+    ms_dec = timed(decompose_only, args.steps, 5, torch, repeats=3)
+    ms_gather = timed(gather_only, args.steps, 5, torch, repeats=3)
     res = {}
     if not args.no_das:
         das_dev = kk.to_device(su.das_plan)
@@ -414,7 +421,7 @@ def main():
         dws = torch.empty(kk.das_workspace_bytes(su.geom, w.N, su.das_plan), dtype=torch.uint8, device=dev)
         das_steps = max(10, args.steps // 4)
         ms_das = timed(lambda: kk.das_beamform(rf, su.geom, su.das_plan, das_dev, image=dimg, ws=dws),
-                       das_steps, 3, torch)
+                       das_steps, 3, torch, repeats=2)
         res["das_ms"] = ms_das
         print("bench: DAS %.2f us/frame" % (ms_das * 1e3), file=sys.stderr, flush=True)
 

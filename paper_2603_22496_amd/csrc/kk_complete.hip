@@ -273,13 +273,35 @@ __global__ __launch_bounds__(192) void wgrad_kernel(const uint16_t* __restrict__
     if (tid < kWidth) pb[kN * kWidth + tid] = bsum;
 }
 
-// dst[j] (+)= sum over g of part[g * n + j], g in order
-__global__ void sum_parts_kernel(const float* __restrict__ part, int nparts, int n, float* __restrict__ dst) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// dst[j] = sum over g of part[g * n + j].  A block covers kSumCols columns; its threads split
+// the parts into 256 / kSumCols interleaved runs (g = r, r + runs, ...), each summed in order,
+// and the runs are then added in run order: the same order on every call (deterministic), and
+// many loads in flight per column instead of one chain of nparts dependent adds.
+template <int kSumCols>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const float* __restrict__ part, int nparts, int n,
+                                                        float* __restrict__ dst) {
+    constexpr int kRuns = 256 / kSumCols;
+    __shared__ float red[256];
+    const int c = threadIdx.x % kSumCols, r = threadIdx.x / kSumCols;
+    const int j = blockIdx.x * kSumCols + c;
     float s = 0.f;
-    for (int g = 0; g < nparts; ++g) s += part[(size_t)g * n + j];
-    dst[j] = s;
+    if (j < n)
+        for (int g = r; g < nparts; g += kRuns) s += part[(size_t)g * n + j];
+    red[r * kSumCols + c] = s;
+    __syncthreads();
+    if (r == 0 && j < n) {
+        float t = red[c];
+        for (int q = 1; q < kRuns; ++q) t += red[q * kSumCols + c];
+        dst[j] = t;
+    }
+}
+
+hipError_t sum_parts(const float* part, int nparts, int n, float* dst, hipStream_t st) {
+    if (n >= 32)
+        hipLaunchKernelGGL(sum_parts_kernel<32>, dim3((n + 31) / 32), dim3(256), 0, st, part, nparts, n, dst);
+    else
+        hipLaunchKernelGGL(sum_parts_kernel<1>, dim3(n), dim3(256), 0, st, part, nparts, n, dst);
+    return hipGetLastError();
 }
 
 // Masked squared error of the network output against the target (unobserved pairs only):
@@ -517,9 +539,8 @@ hipError_t wgrad(int l, const uint16_t* g, const uint16_t* mask, const uint16_t*
     else
         hipLaunchKernelGGL(wgrad_kernel<kWidth>, dim3(w.wg_blocks), dim3(192), 0, st, g, mask, x, sidx, part, B, H,
                            W, w.rows_per_block, dh, dw);
-    const int n = layer_wsize(l) + kWidth;
-    hipLaunchKernelGGL(sum_parts_kernel, dim3((n + 255) / 256), dim3(256), 0, st, part, w.wg_blocks, n, dst);
-    return hipGetLastError();
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    return sum_parts(part, w.wg_blocks, layer_wsize(l) + kWidth, dst, st);
 }
 
 }  // namespace
@@ -608,7 +629,7 @@ int32_t kk_net_backward(void* state, const uint16_t* grid, const float* target, 
     float* lpart = reinterpret_cast<float*>(wsb + w.loss);
     hipLaunchKernelGGL(masked_loss_kernel, dim3(lblocks), dim3(256), 0, st, reinterpret_cast<const float2*>(out),
                        reinterpret_cast<const float2*>(target), grid, sidx, B, HW, inv_count, g[0], lpart);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, st, lpart, lblocks, 1, loss);
+    if (sum_parts(lpart, lblocks, 1, loss, st) != hipSuccess) return KK_E_HIP;
     hipLaunchKernelGGL(scale_kernel, dim3(1), dim3(64), 0, st, loss, inv_count);
     float* part = reinterpret_cast<float*>(wsb + w.part);
     int cur = 0;
