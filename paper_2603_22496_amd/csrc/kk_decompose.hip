@@ -35,7 +35,13 @@ constexpr int kChunkL = 16;                  // elements per LDS chunk
 // column c's operand reads land on banks 2c, 2c+1, so a wave's 32 columns x {Re, Im} hit all
 // 64 banks once.
 constexpr int kRowFloats = kChunkL * kBinBlock * 2 + 2;
-constexpr int kStages = 4;                   // chunks whose global loads are in flight
+// Chunks whose global loads are in flight.  Two measure faster than four or eight: the loop is
+// bound by LDS traffic and barriers rather than by load latency, and fewer register stages
+// leave fewer zero chunks at the end of a ragged element count.
+constexpr int kStages = 2;
+// Phases of one element of a chunk: 8 bins x 16 angles, then a pad of 16 (288 words, 32 modulo
+// the 64 banks): the phase stores of a wave (two elements per 32-lane half) cover every bank once.
+constexpr int kWsL = kBinBlock * 16 + 16;
 
 // exp(+2 pi i ((k s) mod (n 2^22)) / (n 2^22)) for 0 <= k < 2^23, any int32 s: the turn count
 // is reduced exactly with 24-bit products (k s = k s_hi 2^22 + k s_lo, s_lo < 2^22), the coarse
@@ -123,7 +129,7 @@ __device__ __forceinline__ void contract_store(const ContractStage& st, float* x
         const float2 w[8] = {w0, w1, w2, w3, cmul2(w0, d4), cmul2(w1, d4), cmul2(w2, d4), cmul2(w3, d4)};
         const float2 zero = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int b = 0; b < kBinBlock; ++b) ws[(ll * kBinBlock + b) * 16 + ol] = valid ? w[b] : zero;
+        for (int b = 0; b < kBinBlock; ++b) ws[ll * kWsL + b * 16 + ol] = valid ? w[b] : zero;
     }
 }
 
@@ -141,7 +147,7 @@ __device__ __forceinline__ void read_operands(ChunkOperands& op, const float* xs
 #pragma unroll
     for (int ll = 0; ll < kChunkL; ++ll) {
         op.b[ll] = xrow[ll * kBinBlock * 2];
-        op.a[ll] = __uint_as_float(__float_as_uint(wrow[ll * kBinBlock * 16 * 2]) ^ negmask);
+        op.a[ll] = __uint_as_float(__float_as_uint(wrow[ll * kWsL * 2]) ^ negmask);
     }
 }
 
@@ -156,7 +162,7 @@ __device__ __forceinline__ void chunk_mfma(floatx16 (&acc)[2], const ChunkOperan
 // Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] over all elements in chunks of 16.  Software pipeline
 // across chunks, one workgroup barrier per chunk: while the MFMAs of chunk c run from
 // registers, the operands of chunk c+1 are read from LDS and chunk c+2 (spectrum rows and its
-// phases) is written to LDS from its register stage, whose global loads were issued kStages-2
+// phases) is written to LDS from its register stage, whose global loads were issued kStages
 // chunks earlier.  The results leave through LDS as 64-byte runs (8 bins of one (i, o)).
 template <int LOG2N>
 __device__ __forceinline__ void contract_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
@@ -165,7 +171,7 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
     constexpr int N = 1 << LOG2N;
     __shared__ float2 fac[64 + N / 64];
     __shared__ __attribute__((aligned(16))) float xs[2][32 * kRowFloats];
-    __shared__ float2 ws[2][kChunkL * kBinBlock * 16];            // [l][bin][angle]
+    __shared__ float2 ws[2][kChunkL * kWsL];                      // [l][bin][angle] (+ pad per l)
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     build_phase_factors<LOG2N>(fac, tid);
