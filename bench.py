@@ -18,6 +18,9 @@ compounding.  Selection, delay tables and plans are per-geometry setup, built be
                    bound; traffic from the committed PMC byte-counter summary when it matches
                    the kernel source, else null
   stage_rooflines  every stage of the frame against its own bound, from live stage timings
+  graph            the same frame captured as one HIP graph: replays checked against the eager
+                   frame, mean replay time and the p10 / median / p90 of single replays
+  clocks           shader / memory clocks reported by rocm-smi during the run
   cpu_baseline     the FP64 oracle, unmodified, on a bounded sample on this host
 """
 import argparse
@@ -104,6 +107,71 @@ def timed(fn, steps, warmup, torch, repeats=1):
         ms = e0.elapsed_time(e1) / steps
         best = ms if best is None else min(best, ms)
     return best
+
+
+def graph_report(frame, img, inten, args, torch, np):
+    """One frame (decomposition, gather, Eq. 9 intensity) captured as a HIP graph: outputs of
+    three replays (eager work between them) against the eager frame, the mean frame time over
+    args.steps back-to-back replays and the spread of 100 individually timed replays."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        frame()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref_img, ref_int = img.clone(), inten.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        frame()
+    identical = True
+    for _ in range(3):
+        img.zero_()
+        inten.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        identical &= bool(torch.equal(img, ref_img)) and bool(torch.equal(inten, ref_int))
+        frame()                                   # eager work between replays
+        torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    mean_us = e0.elapsed_time(e1) / args.steps * 1e3
+    per = []
+    for _ in range(100):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        b.synchronize()
+        per.append(a.elapsed_time(b) * 1e3)
+    del g
+    p10, p50, p90 = np.percentile(per, [10, 50, 90])
+    return {"identical_to_eager": identical, "frame_us_mean": round(mean_us, 2),
+            "frame_us_p10": round(float(p10), 2), "frame_us_median": round(float(p50), 2),
+            "frame_us_p90": round(float(p90), 2), "replays": args.steps}
+
+
+def gpu_clocks():
+    """Current shader and memory clocks as rocm-smi prints them (None where it is unavailable)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                           text=True, timeout=20)
+    except (OSError, subprocess.SubprocessError):
+        return None
+    found = {}
+    for line in r.stdout.splitlines():
+        for key in ("sclk", "mclk", "fclk"):
+            if key in line and "(" in line and key not in found:
+                found[key] = line.split("(")[-1].split(")")[0].strip()
+    return found or None
 
 
 def precision_report(kk, C, torch, np, args):
@@ -412,6 +480,9 @@ def main():
     print("bench: %d KK frames in %.3fs wall, %.2f us/frame" % (args.steps, wall, ms * 1e3), file=sys.stderr,
           flush=True)
 
+    graph_rep = graph_report(frame, img, inten, args, torch, np)
+    print("bench: graph replay %s" % json.dumps(graph_rep), file=sys.stderr, flush=True)
+
     ms_dec = timed(decompose_only, args.steps, 5, torch, repeats=3)
     ms_gather = timed(gather_only, args.steps, 5, torch, repeats=3)
     res = {}
@@ -519,6 +590,8 @@ def main():
             "pixel_pairs_per_launch": pixpair,
         },
         "stage_rooflines": stage_roofs,
+        "graph": graph_rep,
+        "clocks": gpu_clocks(),
     }
     if "precision" in res:
         out["precision_large"] = res["precision"]
