@@ -158,6 +158,44 @@ def graph_report(frame, img, inten, args, torch, np):
             "frame_us_p90": round(float(p90), 2), "replays": args.steps}
 
 
+def oracle_stage_seconds(O, ds, su, S, w):
+    """Seconds per stage of one oracle frame (the oracle's own stage functions, in its order):
+    analytic spectrum, per-bin contraction (Eq. 3), inverse transform, gather (Eq. 5)."""
+    import numpy as np
+    from oracle.decompose import shear_phases
+    from oracle.spectrum import analytic_spectrum, inverse_bins
+    t = time.time()
+    A = analytic_spectrum(ds.rf, su.tpad)
+    t_fft = time.time() - t
+    shift = su.luts["shift"]
+    Y = np.empty((A.shape[0], shift.shape[0], A.shape[2]), dtype=np.complex128)
+    t = time.time()
+    for o in range(shift.shape[0]):
+        W = shear_phases(shift[o:o + 1], su.tpad)[0]
+        Y[:, o, :] = (A * W[None, :, :]).sum(axis=1)
+    t_contract = time.time() - t
+    t = time.time()
+    R = inverse_bins(Y, su.tpad, w.T)
+    t_inverse = time.time() - t
+    t = time.time()
+    O.kk_beamform(R, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"], su.luts["lut4"],
+                  su.luts["t0_q"], w.X, w.Z)
+    t_gather = time.time() - t
+    return {"fft": round(t_fft, 3), "contraction": round(t_contract, 3), "inverse": round(t_inverse, 3),
+            "gather": round(t_gather, 3)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def gpu_clocks():
     """Current shader and memory clocks as rocm-smi prints them (None where it is unavailable)."""
     import subprocess
@@ -619,6 +657,7 @@ def main():
                 O.kk_beamform(Rc, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
                               su.luts["lut4"], su.luts["t0_q"], w.X, w.Z)
             dt = (time.time() - t) / args.cpu_frames
+            stages = oracle_stage_seconds(O, ds, su, S, w)
         out["cpu_baseline"] = {
             "value": round(pixpair / dt / 1e9, 5),
             "unit": "Gpixel·pair/s",
@@ -626,6 +665,8 @@ def main():
             "kind": "oracle",
             "sample": "%d full vernier KK frames (decompose + beamform, FP64 numpy), %.2f s/frame = %.3f frames/s"
                       % (args.cpu_frames, dt, 1.0 / dt),
+            "stages_s": stages,
+            "cpu": cpu_model(),
         }
     print(json.dumps(out), flush=True)
 
