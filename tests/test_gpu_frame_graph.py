@@ -83,3 +83,34 @@ def test_frame_graph_replays_equal_eager(kk, case):
                         su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
     got = ref_img[:, xi, zi]
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_frames_in_flight_on_separate_streams(kk):
+    """Three different frames enqueued on three streams at once (each with its own buffers) give
+    the images each gives alone: the library keeps no state between calls."""
+    import torch
+    print("frames in flight on three streams", flush=True)
+    cases = [(C.VERNIER, C.speckle_dataset(C.VERNIER, seed=11 + k, n_scat=2000)) for k in range(3)]
+    bufs = [_frame_buffers(kk, w, ds, torch) for w, ds in cases]
+    alone = []
+    for b in bufs:
+        _frame(kk, b)
+        torch.cuda.synchronize()
+        alone.append((b["img"].cpu().numpy(), b["inten"].cpu().numpy()))
+        b["img"].zero_()
+        b["inten"].zero_()
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in bufs]
+    for rep in range(3):
+        for b, st in zip(bufs, streams):
+            su = b["su"]
+            kk.decompose(b["rf"], su.geom, b["shift"], su.M, su.tpad, out=b["rt"], ws=b["ws"], stream=st)
+            kk.beamform(b["rt"], su.plan, b["plan"], image=b["img"], intensity=b["inten"],
+                        mode=kk.COMPOUND_INCOHERENT, ws=b["bws"], stream=st)
+        torch.cuda.synchronize()
+        for k, b in enumerate(bufs):
+            np.testing.assert_array_equal(b["img"].cpu().numpy(), alone[k][0], err_msg="frame %d rep %d" % (k, rep))
+            np.testing.assert_array_equal(b["inten"].cpu().numpy(), alone[k][1], err_msg="frame %d rep %d" % (k, rep))
+            b["img"].zero_()
+            b["inten"].zero_()
+        torch.cuda.synchronize()
