@@ -23,7 +23,7 @@ Printed: one JSON line.
   stage_rooflines  every stage of the frame against its own bound, from live stage timings
   graph            the same frame captured as one HIP graph: replays checked against the eager
                    frame, mean replay time and the p10 / median / p90 of single replays
-  clocks           shader / memory clocks reported by rocm-smi during the run
+  clocks           shader / memory clock levels the driver reports after the timed loop
   cpu_baseline     the FP64 oracle, unmodified, on a bounded sample on this host
 """
 import argparse
@@ -202,18 +202,19 @@ def cpu_model():
 
 
 def gpu_clocks():
-    """Current shader and memory clocks as rocm-smi prints them (None where it is unavailable)."""
-    import subprocess
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
-                           text=True, timeout=20)
-    except (OSError, subprocess.SubprocessError):
-        return None
+    """Current shader and memory clock levels as the amdgpu driver's sysfs files mark them (None
+    where they are unavailable).  Read as files: no helper program is started."""
+    import glob
     found = {}
-    for line in r.stdout.splitlines():
-        for key in ("sclk", "mclk", "fclk"):
-            if key in line and "(" in line and key not in found:
-                found[key] = line.split("(")[-1].split(")")[0].strip()
+    for key, name in (("sclk", "pp_dpm_sclk"), ("mclk", "pp_dpm_mclk"), ("fclk", "pp_dpm_fclk")):
+        for path in sorted(glob.glob("/sys/class/drm/card*/device/" + name)):
+            try:
+                with open(path) as f:
+                    for line in f:
+                        if line.rstrip().endswith("*"):
+                            found.setdefault(key, line.split(":", 1)[-1].replace("*", "").strip())
+            except OSError:
+                continue
     return found or None
 
 
