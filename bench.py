@@ -23,7 +23,7 @@ Printed: one JSON line.
   stage_rooflines  every stage of the frame against its own bound, from live stage timings
   graph            the same frame captured as one HIP graph: replays checked against the eager
                    frame, mean replay time and the p10 / median / p90 of single replays
-  clocks           shader / memory clock levels the driver reports after the timed loop
+  clocks           shader / memory clock levels the amdgpu kernel driver reports after the timed loop
   cpu_baseline     the FP64 oracle, unmodified, on a bounded sample on this host
 """
 import argparse
@@ -464,8 +464,8 @@ def study_report(np):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the KK path shards frame-parallel across GPUs "
-              "(see DESIGN.md) but no multi-GPU run is provided", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); KK frames would shard frame-parallel across GPUs, "
+              "but no multi-GPU path is provided", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

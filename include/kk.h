@@ -65,7 +65,7 @@ typedef enum kk_status {
     KK_E_WORKSPACE = -4,   /* workspace or plan buffer too small or not a valid plan      */
     KK_E_RANGE = -5,       /* a delay does not fit the int32 fixed-point tables           */
     KK_E_HIP = -6,         /* a HIP runtime call or kernel launch failed                  */
-    KK_E_UNSUPPORTED = -7  /* valid request this build does not implement                 */
+    KK_E_UNSUPPORTED = -7  /* valid request the library does not implement               */
 } kk_status;
 
 /* Receive-angle selection schemes (Sec. II-C, II-D). */
