@@ -606,19 +606,31 @@ def main():
         res["das_ms"] = ms_das
         print("bench: DAS %.2f us/frame" % (ms_das * 1e3), file=sys.stderr, flush=True)
 
+    def section(name, fn):
+        """An extra report: a Python-level failure in it is recorded in the JSON line instead of
+        ending the run before the headline is printed."""
+        try:
+            return fn()
+        except Exception as exc:
+            import traceback
+            traceback.print_exc()
+            print("bench: %s section failed: %s" % (name, exc), file=sys.stderr, flush=True)
+            return {"error": "%s: %s" % (type(exc).__name__, exc)}
+
     if not args.no_precision:
-        res["precision"] = precision_report(kk, C, torch, np, args)
+        res["precision"] = section("precision", lambda: precision_report(kk, C, torch, np, args))
 
     if not args.no_ensemble:
-        res["ensemble"] = ensemble_report(kk, C, torch, np, args)
+        res["ensemble"] = section("ensemble", lambda: ensemble_report(kk, C, torch, np, args))
 
     if not args.no_completion:
-        res["completion"] = completion_report(kk, C, torch, np, args)
-        print("bench: completion %s" % json.dumps(res["completion"]["rel_l2_vs_fully_sampled_gpu"]), file=sys.stderr,
-              flush=True)
+        res["completion"] = section("completion", lambda: completion_report(kk, C, torch, np, args))
+        if "error" not in res["completion"]:
+            print("bench: completion %s" % json.dumps(res["completion"]["rel_l2_vs_fully_sampled_gpu"]),
+                  file=sys.stderr, flush=True)
 
     if not args.no_study:
-        res["study"] = study_report(np)
+        res["study"] = section("study", lambda: study_report(np))
 
     if args.copy_mb > 0:
         src = torch.empty(args.copy_mb << 20, dtype=torch.uint8, device=dev)
