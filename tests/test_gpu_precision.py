@@ -80,6 +80,35 @@ def test_vernier_frame_per_dtype(kk, prec_name):
     assert _rel(img.cpu().numpy(), img32.cpu().numpy()) <= _tol(kk, prec)
 
 
+@pytest.fixture(scope="module")
+def large_case(kk):
+    """The large workload at full size (192 elements, 75 transmits, 4096 samples, FFT length 8192,
+    Eq. 6 j = 0, 37, 1350 pair slots, 384 x 768 pixels) with its FP64 oracle records."""
+    w = C.LARGE
+    ds = C.speckle_dataset(w, seed=3, n_scat=20_000)
+    su = kk.make_setup(w)
+    return w, ds, su, O.decompose(ds.rf, su.luts["shift"], su.tpad)
+
+
+@pytest.mark.parametrize("prec_name", ["PREC_FP32", "PREC_BF16X3", "PREC_FP16X3"])
+def test_large_frame_full_size(kk, large_case, prec_name):
+    import torch
+    prec = getattr(kk, prec_name)
+    w, ds, su, R64 = large_case
+    print("large frame", prec_name, flush=True)
+    rf, sh, pd = kk.to_device(ds.rf), kk.to_device(su.luts["shift"]), kk.to_device(su.plan)
+    rt = kk.decompose(rf, su.geom, sh, su.M, su.tpad, precision=prec)
+    img = kk.beamform(rt, su.plan, pd)
+    torch.cuda.synchronize()
+    tol = 1e-5 if prec == kk.PREC_FP32 else _tol(kk, prec)
+    assert _rel(rt.cpu().numpy(), R64) <= tol
+    rng = np.random.default_rng(4)
+    xi, zi = rng.integers(0, w.X, 300), rng.integers(0, w.Z, 300)
+    ref = O.kk_beamform(R64, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
+                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    assert _rel(img.cpu().numpy()[:, xi, zi], ref) <= tol
+
+
 def test_precision_errors(kk):
     import torch
     w = C.TINY
