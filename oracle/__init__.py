@@ -28,7 +28,7 @@ from .geometry import element_positions, tx_angles, grid_axis, next_pow2
 from .selection import select_pairs, SHIFTED, CONFOCAL, SAME, FULL_UNIFORM
 from .luts import build_luts, das_rx_table, fft_length
 from .spectrum import analytic_spectrum, inverse_bins, analytic_signal
-from .decompose import decompose
+from .decompose import decompose, decompose_spectrum
 from .beamform import kk_beamform, das_beamform, lerp_gather
 from .compound import coherent, incoherent, intensity
 
@@ -37,6 +37,6 @@ __all__ = [
     "select_pairs", "SHIFTED", "CONFOCAL", "SAME", "FULL_UNIFORM",
     "build_luts", "das_rx_table", "fft_length",
     "analytic_spectrum", "inverse_bins", "analytic_signal",
-    "decompose", "kk_beamform", "das_beamform", "lerp_gather",
+    "decompose", "decompose_spectrum", "kk_beamform", "das_beamform", "lerp_gather",
     "coherent", "incoherent", "intensity",
 ]

@@ -204,6 +204,18 @@ def _stream(stream) -> int:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _bind(stream, *allocated):
+    """Tensors this module allocated for a call on an explicit stream are marked as used by
+    that stream, so that torch's caching allocator does not hand their memory to another
+    allocation before the enqueued kernels have finished with it."""
+    if stream is None:
+        return
+    s = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(_stream(stream))
+    for t in allocated:
+        if t is not None:
+            t.record_stream(s)
+
+
 def geom(L, T, pitch, c, fs, t0=0.0) -> Geom:
     return Geom(L, T, pitch, c, fs, t0)
 
@@ -299,13 +311,17 @@ def decompose(rf, g: Geom, shift_q, M: int, tpad: int, out=None, ws=None, precis
               stream=None):
     """rf int16 [N][L][T] and shift_q int32 [M][L] on the device -> complex64 [N][M][T]."""
     N = rf.shape[0]
+    new = []
     if out is None:
         out = torch.empty((N, M, g.T), dtype=torch.complex64, device=rf.device)
+        new.append(out)
     nbytes = decompose_workspace_bytes(g, N, M, tpad, precision)
     if ws is None:
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=rf.device)
+        new.append(ws)
     st = lib().kk_decompose(_dev(rf), N, ctypes.byref(g), _dev(shift_q), M, tpad, precision, _dev(out),
                             _dev(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _bind(stream, *new)
     _check("kk_decompose", st)
     return out
 
@@ -319,24 +335,31 @@ def beamform(rf_theta, plan_host: np.ndarray, plan_dev, image=None, intensity=No
     """rf_theta complex64 [N][M][T] -> per-set images complex64 [S][X][Z] (and intensity)."""
     N, M, T = rf_theta.shape
     S, X, Z = int(plan_host[6]), int(plan_host[7]), int(plan_host[8])
+    new = []
     if image is None:
         image = torch.empty((S, X, Z), dtype=torch.complex64, device=rf_theta.device)
+        new.append(image)
     need = beamform_workspace_bytes(plan_host)
     if ws is None and need > 0:
         ws = torch.empty(need, dtype=torch.uint8, device=rf_theta.device)
+        new.append(ws)
     st = lib().kk_beamform(_dev(rf_theta), N, M, T, plan_host.ctypes.data_as(_vp), _dev(plan_dev),
                            plan_host.nbytes, _dev(image), _dev(intensity) if intensity is not None else None,
                            mode, _dev(ws) if ws is not None else None,
                            ws.numel() * ws.element_size() if ws is not None else 0, _stream(stream))
+    _bind(stream, *new)
     _check("kk_beamform", st)
     return image
 
 
 def compound(image, mode: int = COMPOUND_COHERENT, out=None, stream=None):
     S, X, Z = image.shape
+    new = None
     if out is None:
-        out = torch.empty((X, Z), dtype=torch.float32, device=image.device)
-    _check("kk_compound", lib().kk_compound(_dev(image), S, X, Z, mode, _dev(out), _stream(stream)))
+        out = new = torch.empty((X, Z), dtype=torch.float32, device=image.device)
+    st = lib().kk_compound(_dev(image), S, X, Z, mode, _dev(out), _stream(stream))
+    _bind(stream, new)
+    _check("kk_compound", st)
     return out
 
 
@@ -347,14 +370,18 @@ def das_workspace_bytes(g: Geom, N: int, plan_host: np.ndarray) -> int:
 def das_beamform(rf, g: Geom, plan_host: np.ndarray, plan_dev, image=None, ws=None, stream=None):
     N = rf.shape[0]
     X, Z = int(plan_host[7]), int(plan_host[8])
+    new = []
     if image is None:
         image = torch.empty((X, Z), dtype=torch.complex64, device=rf.device)
+        new.append(image)
     nbytes = das_workspace_bytes(g, N, plan_host)
     if ws is None:
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=rf.device)
+        new.append(ws)
     st = lib().das_beamform(_dev(rf), N, ctypes.byref(g), plan_host.ctypes.data_as(_vp), _dev(plan_dev),
                             plan_host.nbytes, _dev(image), _dev(ws), ws.numel() * ws.element_size(),
                             _stream(stream))
+    _bind(stream, *new)
     _check("das_beamform", st)
     return image
 
@@ -368,14 +395,18 @@ def decompose_spectrum(rf, g: Geom, shift_q, M: int, tpad: int, out=None, ws=Non
     """rf int16 [N][L][T], shift_q int32 [M][L] on the device -> complex64 [N][M][kpad] (bins >= tpad/2 zero)."""
     N = rf.shape[0]
     kpad = spectrum_bins(tpad)
+    new = []
     if out is None:
         out = torch.empty((N, M, kpad), dtype=torch.complex64, device=rf.device)
+        new.append(out)
     nbytes = decompose_workspace_bytes(g, N, M, tpad, precision)
     if ws is None:
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=rf.device)
-    _check("kk_decompose_spectrum", lib().kk_decompose_spectrum(_dev(rf), N, ctypes.byref(g), _dev(shift_q), M, tpad,
-                                                                precision, _dev(out), _dev(ws),
-                                                                ws.numel() * ws.element_size(), _stream(stream)))
+        new.append(ws)
+    st = lib().kk_decompose_spectrum(_dev(rf), N, ctypes.byref(g), _dev(shift_q), M, tpad, precision, _dev(out),
+                                     _dev(ws), ws.numel() * ws.element_size(), _stream(stream))
+    _bind(stream, *new)
+    _check("kk_decompose_spectrum", st)
     return out
 
 
@@ -383,9 +414,12 @@ def spectrum_inverse(spec, tpad: int, T: int, out=None, stream=None):
     """spec complex64 [..., kpad] -> complex64 [..., T] (first T samples of the inverse transform)."""
     lead = spec.shape[:-1]
     n = int(np.prod(lead))
+    new = None
     if out is None:
-        out = torch.empty(tuple(lead) + (T,), dtype=torch.complex64, device=spec.device)
-    _check("kk_spectrum_inverse", lib().kk_spectrum_inverse(_dev(spec), n, tpad, T, _dev(out), _stream(stream)))
+        out = new = torch.empty(tuple(lead) + (T,), dtype=torch.complex64, device=spec.device)
+    st = lib().kk_spectrum_inverse(_dev(spec), n, tpad, T, _dev(out), _stream(stream))
+    _bind(stream, new)
+    _check("kk_spectrum_inverse", st)
     return out
 
 

@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +35,12 @@ def kk():
 
 
 def _case(K, w, ds, scheme=None, M=None, jl=None, seed=0):
+    """Library setup, the oracle's tables (checked equal to the library's) and the oracle's
+    RF_theta rounded to complex64."""
     su = K.make_setup(w, scheme=scheme, M=M, j_list=jl)
-    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
-    R32 = R.astype(np.complex64)
-    return su, R32
+    ot = OR.tables(su, w, scheme, M, jl)
+    R32 = ot.decompose(ds.rf).astype(np.complex64)
+    return su, ot, R32
 
 
 SPLIT_WORD = 24    # plan header word: pair shares per (set, tile)
@@ -53,10 +56,8 @@ def _run(K, su, R32, plan=None):
     return img.cpu().numpy()
 
 
-def _oracle_img(su, R32, pixels=None):
-    return O.kk_beamform(R32.astype(np.complex128), su.sel["pairs"], su.sel["S"], su.luts["lut1"],
-                         su.luts["lut2"], su.luts["lut3"], su.luts["lut4"], su.luts["t0_q"],
-                         su.grid.X, su.grid.Z, pixels=pixels)
+def _oracle_img(ot, R32, pixels=None):
+    return ot.kk_image(rf_theta=R32.astype(np.complex128), pixels=pixels)
 
 
 @pytest.mark.parametrize("scheme,M,jl", [
@@ -66,9 +67,9 @@ def _oracle_img(su, R32, pixels=None):
 ])
 def test_tiny_all_pixels(kk, scheme, M, jl):
     ds = C.tiny_dataset(0)
-    su, R32 = _case(kk, C.TINY, ds, scheme, M, jl)
+    su, ot, R32 = _case(kk, C.TINY, ds, scheme, M, jl)
     got = _run(kk, su, R32)
-    ref = _oracle_img(su, R32)
+    ref = _oracle_img(ot, R32)
     assert got.shape == ref.shape
     assert _rel(got, ref) <= TOL_BF, _rel(got, ref)
 
@@ -80,9 +81,9 @@ def test_ragged_grid_and_record_edges(kk):
     acq = w.acquisition()
     from paper_2603_22496_amd.phantom import make_dataset, seeded_points
     ds = make_dataset(acq, seeded_points(11, z_range=(4e-3, 12e-3)))
-    su, R32 = _case(kk, w, ds, C.SCHEME_SHIFTED, 5, (0, 2))
+    su, ot, R32 = _case(kk, w, ds, C.SCHEME_SHIFTED, 5, (0, 2))
     got = _run(kk, su, R32)
-    ref = _oracle_img(su, R32)
+    ref = _oracle_img(ot, R32)
     assert _rel(got, ref) <= TOL_BF
 
 
@@ -90,10 +91,11 @@ def test_random_record_values(kk):
     # arbitrary complex records (not band-limited) exercise every lerp weight and edge
     w = replace(C.TINY, X=128, Z=48)
     su = kk.make_setup(w, scheme=C.SCHEME_SHIFTED, M=7, j_list=(0, 2))
+    ot = OR.tables(su, w, C.SCHEME_SHIFTED, 7, (0, 2))
     rng = np.random.default_rng(3)
     R32 = (rng.standard_normal((w.N, su.M, w.T)) + 1j * rng.standard_normal((w.N, su.M, w.T))).astype(np.complex64)
     got = _run(kk, su, R32)
-    ref = _oracle_img(su, R32)
+    ref = _oracle_img(ot, R32)
     assert _rel(got, ref) <= TOL_BF
 
 
@@ -102,8 +104,8 @@ def test_pair_split_factors(kk):
     # (more shares than batches), and the partial images summed in the fixed order
     w = replace(C.TINY, X=70, Z=37)
     ds = C.tiny_dataset(6)
-    su, R32 = _case(kk, w, ds, C.SCHEME_SHIFTED, 5, (0, 1))
-    ref = _oracle_img(su, R32)
+    su, ot, R32 = _case(kk, w, ds, C.SCHEME_SHIFTED, 5, (0, 1))
+    ref = _oracle_img(ot, R32)
     base = _run(kk, su, R32)
     for k in (1, 2, 3, 5, 8):
         plan = su.plan.copy()
@@ -119,7 +121,7 @@ def test_pair_split_factors(kk):
 def test_full_size_sampled_pixels(kk, wname):
     w = C.WORKLOADS[wname]
     ds = C.speckle_dataset(C.VERNIER, seed=2, n_scat=20000)
-    su, R32 = _case(kk, w, ds)
+    su, ot, R32 = _case(kk, w, ds)
     if wname == "full":   # one set: fewer tiles than CUs, the plan splits the pairs
         assert su.plan[SPLIT_WORD] > 1
     got = _run(kk, su, R32)
@@ -129,28 +131,28 @@ def test_full_size_sampled_pixels(kk, wname):
     # tile corners and the grid edges too
     xi = np.concatenate([xi, [0, w.X - 1, 63, 64, 0, w.X - 1]])
     zi = np.concatenate([zi, [0, w.Z - 1, 15, 16, w.Z - 1, 0]])
-    ref = _oracle_img(su, R32, pixels=(xi, zi))
+    ref = _oracle_img(ot, R32, pixels=(xi, zi))
     assert _rel(got[:, xi, zi], ref) <= TOL_BF
 
 
 def test_compounding_matches_oracle(kk):
     import torch
     ds = C.tiny_dataset(4)
-    su, R32 = _case(kk, C.TINY, ds, C.SCHEME_SHIFTED, 5, (0, 1, 2))
+    su, ot, R32 = _case(kk, C.TINY, ds, C.SCHEME_SHIFTED, 5, (0, 1, 2))
     rt, pd = kk.to_device(R32), kk.to_device(su.plan)
     for mode, fn in ((kk.COMPOUND_COHERENT, O.coherent), (kk.COMPOUND_INCOHERENT, O.incoherent)):
         inten = torch.empty((su.grid.X, su.grid.Z), dtype=torch.float32, device="cuda")
         img = kk.beamform(rt, su.plan, pd, intensity=inten, mode=mode)
         I2 = kk.compound(img, mode)
         torch.cuda.synchronize()
-        ref = fn(_oracle_img(su, R32))
+        ref = fn(_oracle_img(ot, R32))
         assert _rel(inten.cpu().numpy(), ref) <= 2 * TOL_BF
         assert np.array_equal(inten.cpu().numpy(), I2.cpu().numpy())
 
 
 def test_deterministic(kk):
     ds = C.tiny_dataset(5)
-    su, R32 = _case(kk, C.TINY, ds)
+    su, ot, R32 = _case(kk, C.TINY, ds)
     a = _run(kk, su, R32)
     b = _run(kk, su, R32)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
@@ -164,7 +166,7 @@ def test_deterministic(kk):
 def test_argument_errors(kk):
     import torch
     ds = C.tiny_dataset(0)
-    su, R32 = _case(kk, C.TINY, ds)
+    su, ot, R32 = _case(kk, C.TINY, ds)
     rt, pd = kk.to_device(R32), kk.to_device(su.plan)
     with pytest.raises(kk.KKError) as e:          # record count differs from the plan's
         kk.beamform(rt[:, :-1].contiguous(), su.plan, pd)

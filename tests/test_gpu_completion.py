@@ -13,6 +13,7 @@ import oracle as O
 from oracle import completion as OC
 from oracle.decompose import decompose_spectrum as oracle_spectrum
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -269,7 +270,8 @@ def test_spectrum_and_inverse_match_oracle(kk):
     su = kk.make_setup(C.TINY)
     spec = kk.decompose_spectrum(kk.to_device(ds.rf), su.geom, kk.to_device(su.luts["shift"]), su.M, su.tpad)
     torch.cuda.synchronize()
-    Y = oracle_spectrum(ds.rf, su.luts["shift"], su.tpad)             # [N][M][K]
+    ot = OR.tables(su, C.TINY)
+    Y = oracle_spectrum(ds.rf, ot.luts["shift"], ot.luts["tpad"])     # [N][M][K]
     kpad = kk.spectrum_bins(su.tpad)
     got = spec.cpu().numpy()
     half = su.tpad // 2

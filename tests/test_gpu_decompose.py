@@ -10,7 +10,9 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import frame as OF
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 from paper_2603_22496_amd.phantom import Acquisition, make_dataset, seeded_points
 
 pytestmark = pytest.mark.gpu
@@ -46,7 +48,7 @@ def test_tiny_rf_theta(kk):
     ds = C.tiny_dataset(0)
     su = kk.make_setup(w)
     got = _decompose_gpu(kk, ds.rf, w.L, w.T, su.luts["shift"], su.tpad)
-    ref = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    ref = OR.tables(su, w).decompose(ds.rf)
     assert _rel(got, ref) <= TOL, _rel(got, ref)
 
 
@@ -77,7 +79,7 @@ def test_vernier_rf_theta(kk):
     ds = C.speckle_dataset(w, seed=2, n_scat=20000)
     su = kk.make_setup(w)
     got = _decompose_gpu(kk, ds.rf, w.L, w.T, su.luts["shift"], su.tpad)
-    ref = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    ref = OR.tables(su, w).decompose(ds.rf)
     assert _rel(got, ref) <= TOL, _rel(got, ref)
 
 
@@ -87,7 +89,8 @@ def test_full_bank_rf_theta_sampled_angles(kk):
     su = kk.make_setup(w)
     got = _decompose_gpu(kk, ds.rf, w.L, w.T, su.luts["shift"], su.tpad)
     pick = [0, 1, 17, 63, 64, 100, 126, 127]
-    ref = O.decompose(ds.rf, su.luts["shift"][pick], su.tpad)
+    ot = OR.tables(su, w)
+    ref = O.decompose(ds.rf, ot.luts["shift"][pick], ot.luts["tpad"])
     assert _rel(got[:, pick], ref) <= TOL, _rel(got[:, pick], ref)
 
 
@@ -109,9 +112,7 @@ def test_tiny_end_to_end_image(kk, scheme, M, jl):
     ds = C.tiny_dataset(7)
     su = kk.make_setup(w, scheme=scheme, M=M, j_list=jl)
     got = _frame(kk, su, ds.rf)
-    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
-    ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z)
+    ref = OR.tables(su, w, scheme, M, jl).kk_image(ds.rf)
     assert _rel(got, ref) <= TOL, _rel(got, ref)
 
 
@@ -120,11 +121,9 @@ def test_vernier_end_to_end_image_sampled(kk):
     ds = C.speckle_dataset(w, seed=2, n_scat=100000)
     su = kk.make_setup(w)
     got = _frame(kk, su, ds.rf)
-    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
     rng = np.random.default_rng(9)
     xi, zi = rng.integers(0, w.X, 600), rng.integers(0, w.Z, 600)
-    ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    ref = OR.tables(su, w).kk_image(ds.rf, pixels=(xi, zi))
     assert _rel(got[:, xi, zi], ref) <= TOL, _rel(got[:, xi, zi], ref)
 
 
@@ -138,15 +137,14 @@ def _das(K, w, rf):
     plan = K.das_plan(w.N, g, luts, rx, gr)
     img = K.das_beamform(K.to_device(rf), g, plan, K.to_device(plan))
     torch.cuda.synchronize()
-    return img.cpu().numpy(), luts, rx
+    return img.cpu().numpy(), OR.das_tables(w, luts, rx)
 
 
 def test_das_tiny_all_pixels(kk):
     w = C.TINY
     ds = C.tiny_dataset(1)
-    got, luts, rx = _das(kk, w, ds.rf)
-    rfa = O.analytic_signal(ds.rf, O.next_pow2(w.T))
-    ref = O.das_beamform(rfa, luts["lut1"], luts["lut2"], rx, luts["t0_q"], w.X, w.Z)
+    got, luts = _das(kk, w, ds.rf)
+    ref = OF.das_image(ds.rf, luts, w.X, w.Z)
     assert _rel(got, ref) <= TOL, _rel(got, ref)
 
 
@@ -154,20 +152,18 @@ def test_das_ragged_and_late_start(kk):
     w = replace(C.TINY, X=70, Z=37, t0=3e-6, T=1000)
     acq = w.acquisition()
     ds = make_dataset(acq, seeded_points(12))
-    got, luts, rx = _das(kk, w, ds.rf)
-    rfa = O.analytic_signal(ds.rf, O.next_pow2(w.T))
-    ref = O.das_beamform(rfa, luts["lut1"], luts["lut2"], rx, luts["t0_q"], w.X, w.Z)
+    got, luts = _das(kk, w, ds.rf)
+    ref = OF.das_image(ds.rf, luts, w.X, w.Z)
     assert _rel(got, ref) <= TOL, _rel(got, ref)
 
 
 def test_das_vernier_sampled(kk):
     w = C.VERNIER
     ds = C.speckle_dataset(w, seed=2, n_scat=20000)
-    got, luts, rx = _das(kk, w, ds.rf)
-    rfa = O.analytic_signal(ds.rf, O.next_pow2(w.T))
+    got, luts = _das(kk, w, ds.rf)
     rng = np.random.default_rng(10)
     xi, zi = rng.integers(0, w.X, 300), rng.integers(0, w.Z, 300)
-    ref = O.das_beamform(rfa, luts["lut1"], luts["lut2"], rx, luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    ref = OF.das_image(ds.rf, luts, w.X, w.Z, pixels=(xi, zi))
     assert _rel(got[xi, zi], ref) <= TOL, _rel(got[xi, zi], ref)
 
 

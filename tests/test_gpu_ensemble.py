@@ -11,8 +11,8 @@ autotuned launch shapes must keep the results.
 import numpy as np
 import pytest
 
-import oracle as O
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -119,9 +119,7 @@ def test_ensemble_against_oracle(kk):
     import torch
     torch.cuda.synchronize()
     for f, su in enumerate(sus):
-        R = O.decompose(data[f], su.luts["shift"], su.tpad)
-        ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                            su.luts["lut4"], su.luts["t0_q"], su.grid.X, su.grid.Z)
+        ref = OR.tables(su, ws[f]).kk_image(data[f])
         got = E.frame_image(f).cpu().numpy()
         rel = _rel(got, ref)
         print("frame %d (L %d N %d M %d S %d %dx%d) rel-L2 %.3e" % (f, su.geom.L, su.N, su.M, su.sel["S"],

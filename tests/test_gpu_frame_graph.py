@@ -4,8 +4,8 @@ bit for bit, and the replayed images match the FP64 oracle at sampled pixels."""
 import numpy as np
 import pytest
 
-import oracle as O
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -76,11 +76,9 @@ def test_frame_graph_replays_equal_eager(kk, case):
     del g
     # the replayed frame against the FP64 oracle at sampled pixels
     su = b["su"]
-    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
     rng = np.random.default_rng(0)
     xi, zi = rng.integers(0, w.X, 200), rng.integers(0, w.Z, 200)
-    ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    ref = OR.tables(su, w).kk_image(ds.rf, pixels=(xi, zi))
     got = ref_img[:, xi, zi]
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
 

@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +64,8 @@ def test_vernier_frame_per_dtype(kk, prec_name):
     w = C.VERNIER
     ds = C.speckle_dataset(w, seed=2, n_scat=20000)
     su = kk.make_setup(w)
-    R64 = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    ot = OR.tables(su, w)
+    R64 = ot.decompose(ds.rf)
     rf, sh, pd = kk.to_device(ds.rf), kk.to_device(su.luts["shift"]), kk.to_device(su.plan)
     rt = kk.decompose(rf, su.geom, sh, su.M, su.tpad, precision=prec)
     rt32 = kk.decompose(rf, su.geom, sh, su.M, su.tpad)
@@ -73,8 +75,7 @@ def test_vernier_frame_per_dtype(kk, prec_name):
     assert _rel(rt.cpu().numpy(), R64) <= _tol(kk, prec)
     rng = np.random.default_rng(0)
     xi, zi = rng.integers(0, w.X, 300), rng.integers(0, w.Z, 300)
-    ref = O.kk_beamform(R64, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    ref = ot.kk_image(rf_theta=R64, pixels=(xi, zi))
     assert _rel(img.cpu().numpy()[:, xi, zi], ref) <= _tol(kk, prec)
     # against the FP32 run over the whole image
     assert _rel(img.cpu().numpy(), img32.cpu().numpy()) <= _tol(kk, prec)
@@ -87,14 +88,15 @@ def large_case(kk):
     w = C.LARGE
     ds = C.speckle_dataset(w, seed=3, n_scat=20_000)
     su = kk.make_setup(w)
-    return w, ds, su, O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    ot = OR.tables(su, w)
+    return w, ds, su, ot, ot.decompose(ds.rf)
 
 
 @pytest.mark.parametrize("prec_name", ["PREC_FP32", "PREC_BF16X3", "PREC_FP16X3"])
 def test_large_frame_full_size(kk, large_case, prec_name):
     import torch
     prec = getattr(kk, prec_name)
-    w, ds, su, R64 = large_case
+    w, ds, su, ot, R64 = large_case
     print("large frame", prec_name, flush=True)
     rf, sh, pd = kk.to_device(ds.rf), kk.to_device(su.luts["shift"]), kk.to_device(su.plan)
     rt = kk.decompose(rf, su.geom, sh, su.M, su.tpad, precision=prec)
@@ -104,8 +106,7 @@ def test_large_frame_full_size(kk, large_case, prec_name):
     assert _rel(rt.cpu().numpy(), R64) <= tol
     rng = np.random.default_rng(4)
     xi, zi = rng.integers(0, w.X, 300), rng.integers(0, w.Z, 300)
-    ref = O.kk_beamform(R64, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    ref = ot.kk_image(rf_theta=R64, pixels=(xi, zi))
     assert _rel(img.cpu().numpy()[:, xi, zi], ref) <= tol
 
 

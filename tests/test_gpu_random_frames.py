@@ -7,8 +7,8 @@ from dataclasses import replace
 import numpy as np
 import pytest
 
-import oracle as O
 from paper_2603_22496_amd import configs as C
+from tests import oracle_ref as OR
 
 pytestmark = pytest.mark.gpu
 
@@ -58,10 +58,10 @@ def test_random_frame_against_oracle(kk, case):
     img = kk.beamform(rt, su.plan, kk.to_device(su.plan))
     torch.cuda.synchronize()
     got = img.cpu().numpy()
-    R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    ot = OR.tables(su, w)                          # the oracle's own selection and tables
+    R = ot.decompose(ds.rf)
     np.testing.assert_allclose(rt.cpu().numpy(), R, rtol=0, atol=TOL * float(np.abs(R).max()) * 4)
-    ref = O.kk_beamform(R, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z)
+    ref = ot.kk_image(rf_theta=R)
     for s in range(su.sel["S"]):
         rel = float(np.linalg.norm(got[s] - ref[s]) / np.linalg.norm(ref[s]))
         assert rel <= TOL, (s, rel)

@@ -118,3 +118,73 @@ def test_decomposition_is_linear():
 def test_record_longer_than_fft_is_rejected():
     with pytest.raises(ValueError):
         O.analytic_spectrum(np.zeros((1, 300)), 256)
+
+
+# ---------------------------------------------------------------------------------------
+# Pins of decompose_spectrum (the per-bin contraction of Eq. 3 before the inverse transform)
+
+def test_spectrum_is_the_transform_of_an_integer_shift_and_sum():
+    # integer advances m_l: Eq. 3 is a time-domain shift-and-sum of the length-T' analytic
+    # traces; its forward DFT must be the contraction output bin for bin (and zero above T'/2)
+    rng = np.random.default_rng(11)
+    N, L, T, tp = 2, 5, 90, 128
+    x = rng.integers(-3000, 3000, size=(N, L, T)).astype(np.int16)
+    m = np.array([[0, 1, 2, 3, 4], [9, 0, 17, 5, 33], [0, 0, 0, 0, 0]])
+    Y = O.decompose_spectrum(x, (m << 22).astype(np.int32), tp)
+    full = O.inverse_bins(O.analytic_spectrum(x, tp), tp, tp)
+    for i in range(N):
+        for o in range(m.shape[0]):
+            y = sum(np.roll(full[i, l], -m[o, l]) for l in range(L))
+            F = np.fft.fft(y)
+            scale = np.max(np.abs(F))
+            assert np.max(np.abs(Y[i, o] - F[: tp // 2 + 1])) < 1e-10 * scale
+            assert np.max(np.abs(F[tp // 2 + 1:])) < 1e-10 * scale
+
+
+def test_spectrum_of_bin_centred_cosine_under_fractional_advances():
+    # x = cos(2 pi k0 n / T') over the whole record has one analytic bin, A[k0] = T'; an
+    # advance of s samples multiplies it by exp(2 pi i k0 s / T'), summed over the elements
+    tp, k0 = 256, 37
+    n = np.arange(tp)
+    L = 4
+    x = np.tile(np.cos(2 * np.pi * k0 * n / tp), (1, L, 1))
+    sq = np.array([[0, 1234567, -98765432, 2 ** 31 - 1], [5 << 22, (5 << 22) + 1, 7, -(1 << 30)]],
+                  dtype=np.int64)
+    Y = O.decompose_spectrum(x, sq.astype(np.int32), tp)
+    for o in range(2):
+        expect = sum(tp * complex(math.cos(2 * math.pi * k0 * (s / 2 ** 22) / tp),
+                                  math.sin(2 * math.pi * k0 * (s / 2 ** 22) / tp)) for s in sq[o])
+        assert abs(Y[0, o, k0] - expect) < 1e-9 * tp
+        others = np.delete(Y[0, o], k0)
+        assert np.max(np.abs(others)) < 1e-9 * tp
+
+
+def test_spectrum_direct_dft_brute_force():
+    # L = 4, N = 2, M = 3, T = 64: the analytic DFT of every record and the exactly reduced
+    # phase turns evaluated bin by bin in plain Python
+    rng = np.random.default_rng(12)
+    N, L, M, T, tp = 2, 4, 3, 64, 128
+    x = rng.integers(-32768, 32767, size=(N, L, T)).astype(np.int16)
+    sh = rng.integers(-2 ** 31, 2 ** 31 - 1, size=(M, L)).astype(np.int32)
+    Y = O.decompose_spectrum(x, sh, tp)
+    period = tp << 22
+    for i in range(N):
+        for o in range(M):
+            for k in range(tp // 2 + 1):
+                h = 1.0 if k in (0, tp // 2) else 2.0
+                acc = 0j
+                for l in range(L):
+                    a = sum(float(x[i, l, n]) * complex(math.cos(2 * math.pi * k * n / tp),
+                                                        -math.sin(2 * math.pi * k * n / tp)) for n in range(T))
+                    r = (k * int(sh[o, l])) % period
+                    acc += h * a * complex(math.cos(2 * math.pi * r / period), math.sin(2 * math.pi * r / period))
+                assert abs(Y[i, o, k] - acc) < 1e-7 * (1.0 + abs(acc)), (i, o, k)
+
+
+def test_inverse_of_spectrum_is_the_decomposition():
+    ds = C.tiny_dataset(2)
+    rng = np.random.default_rng(13)
+    sh = rng.integers(-2 ** 31, 2 ** 31 - 1, size=(3, ds.rf.shape[1])).astype(np.int32)
+    Y = O.decompose_spectrum(ds.rf, sh, 2048)
+    R = O.decompose(ds.rf, sh, 2048)
+    assert np.max(np.abs(O.inverse_bins(Y, 2048, ds.rf.shape[2]) - R)) < 1e-12 * np.max(np.abs(R))
