@@ -13,6 +13,7 @@ import os
 import shutil
 import subprocess
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -41,17 +42,15 @@ def _run(cmd, cwd=None):
 def build_libkk(verbose: bool = False, extra_hip_flags=()) -> str:
     tmp = tempfile.mkdtemp(prefix="kkbuild_")
     try:
-        objs = []
-        for src in HOST_SOURCES:
-            o = os.path.join(tmp, src + ".o")
-            _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
-            objs.append(o)
-        for src in HIP_SOURCES:
-            o = os.path.join(tmp, src + ".o")
-            out = _run([HIPCC, *HIP_FLAGS, *extra_hip_flags, "-c", os.path.join(CSRC, src), "-o", o])
-            if verbose and out.strip():
-                print(out)
-            objs.append(o)
+        jobs = [["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(tmp, src + ".o")]
+                for src in HOST_SOURCES]
+        jobs += [[HIPCC, *HIP_FLAGS, *extra_hip_flags, "-c", os.path.join(CSRC, src), "-o", os.path.join(tmp, src + ".o")]
+                 for src in HIP_SOURCES]
+        objs = [j[-1] for j in jobs]
+        with ThreadPoolExecutor(max_workers=min(len(jobs), max(1, min(8, os.cpu_count() or 1)))) as ex:
+            for out in ex.map(_run, jobs):
+                if verbose and out.strip():
+                    print(out)
         tmp_lib = os.path.join(tmp, "libkk.so")
         _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp_lib, "-lgomp"])
         shutil.copy2(tmp_lib, LIB + ".tmp")
