@@ -73,7 +73,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--streams", type=int, default=3, help="frames in flight on separate HIP streams in the timed loop")
     ap.add_argument("--settle-s", type=float, default=0.5, help="seconds of untimed frames before the warm-up steps")
-    ap.add_argument("--cpu-frames", type=int, default=10, help="oracle frames timed for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-frames", type=int, default=32,
+                    help="whole oracle frames timed on the host's cores for cpu_baseline (0: skip)")
+    ap.add_argument("--no-full-bank", action="store_true", help="skip the 128-angle bank frame report")
     ap.add_argument("--no-das", action="store_true")
     ap.add_argument("--no-parity", action="store_true", help="skip the oracle check of the timed frame")
     ap.add_argument("--no-precision", action="store_true",
@@ -165,31 +167,107 @@ def graph_report(frame, img, inten, args, torch, np):
             "frame_us_p90": round(float(p90), 2), "replays": args.steps}
 
 
-def oracle_stage_seconds(O, ds, su, S, w):
-    """Seconds per stage of one oracle frame (the oracle's own stage functions, in its order):
-    analytic spectrum, per-bin contraction (Eq. 3), inverse transform, gather (Eq. 5)."""
+# ---------------------------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands, timed on this host before the GPU is touched (its
+# worker processes are plain forks of a process that has not initialised the GPU).
+
+_CPU = {}
+
+
+def _oracle_vernier_frame(_):
+    """One whole oracle frame (Eq. 3 decomposition, then the Eq. 5 gather of every set) in a
+    forked worker; returns its seconds."""
+    from threadpoolctl import threadpool_limits
+    from oracle import frame as OF
+    with threadpool_limits(limits=1):
+        t = time.time()
+        OF.kk_image(_CPU["rf"], _CPU["sel"], _CPU["luts"], _CPU["X"], _CPU["Z"])
+        return time.time() - t
+
+
+def oracle_stages(ds, sel, luts, w, das_luts=None, das_stride=1):
+    """Seconds per stage of one oracle frame in the paper's Table II columns (FFT, compress,
+    IFFT, beamform; DAS when its tables are given), one thread.  DAS may be evaluated on every
+    das_stride-th pixel only and scaled up (its time is linear in the pixel count)."""
     import numpy as np
+    from oracle import beamform as OB
     from oracle.decompose import shear_phases
-    from oracle.spectrum import analytic_spectrum, inverse_bins
+    from oracle.spectrum import analytic_signal, analytic_spectrum, inverse_bins
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t = time.time()
+        A = analytic_spectrum(ds.rf, luts["tpad"])
+        t_fft = time.time() - t
+        shift = luts["shift"]
+        Y = np.empty((A.shape[0], shift.shape[0], A.shape[2]), dtype=np.complex128)
+        t = time.time()
+        for o in range(shift.shape[0]):
+            W = shear_phases(shift[o:o + 1], luts["tpad"])[0]
+            Y[:, o, :] = (A * W[None, :, :]).sum(axis=1)
+        t_contract = time.time() - t
+        t = time.time()
+        R = inverse_bins(Y, luts["tpad"], w.T)
+        t_inverse = time.time() - t
+        t = time.time()
+        OB.kk_beamform(R, sel["pairs"], sel["S"], luts["lut1"], luts["lut2"], luts["lut3"], luts["lut4"],
+                       luts["t0_q"], w.X, w.Z)
+        t_gather = time.time() - t
+        out = {"fft": t_fft, "compress": t_contract, "ifft": t_inverse, "beamform": t_gather}
+        if das_luts is not None:
+            tp = 1
+            while tp < w.T:
+                tp *= 2
+            t = time.time()
+            rfa = analytic_signal(ds.rf, tp)
+            npix = w.X * w.Z
+            flat = np.arange(0, npix, das_stride)
+            OB.das_beamform(rfa, das_luts["lut1"], das_luts["lut2"], das_luts["rx"], das_luts["t0_q"], w.X, w.Z,
+                            pixels=(flat // w.Z, flat % w.Z))
+            out["das"] = (time.time() - t) * npix / len(flat)
+    return out
+
+
+def cpu_baseline(C, ds, w, frames, log):
+    """The oracle's throughput on this host's cores (min(affinity, 16) forked workers, one frame
+    each at a time, `frames` whole vernier frames), and per-stage single-thread times (median
+    of 3) on the vernier and tiny workloads."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import frame as OF
+    sel, luts = OF.tables(w)
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    _CPU.update(rf=ds.rf, sel=sel, luts=luts, X=w.X, Z=w.Z)
     t = time.time()
-    A = analytic_spectrum(ds.rf, su.tpad)
-    t_fft = time.time() - t
-    shift = su.luts["shift"]
-    Y = np.empty((A.shape[0], shift.shape[0], A.shape[2]), dtype=np.complex128)
-    t = time.time()
-    for o in range(shift.shape[0]):
-        W = shear_phases(shift[o:o + 1], su.tpad)[0]
-        Y[:, o, :] = (A * W[None, :, :]).sum(axis=1)
-    t_contract = time.time() - t
-    t = time.time()
-    R = inverse_bins(Y, su.tpad, w.T)
-    t_inverse = time.time() - t
-    t = time.time()
-    O.kk_beamform(R, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"], su.luts["lut4"],
-                  su.luts["t0_q"], w.X, w.Z)
-    t_gather = time.time() - t
-    return {"fft": round(t_fft, 3), "contraction": round(t_contract, 3), "inverse": round(t_inverse, 3),
-            "gather": round(t_gather, 3)}
+    with mp.get_context("fork").Pool(cores) as pool:
+        per = pool.map(_oracle_vernier_frame, range(frames), chunksize=1)
+    wall = time.time() - t
+    pixpair = w.X * w.Z * len(sel["pairs"])
+    log("cpu baseline: %d oracle frames on %d workers in %.2fs wall (%.2f s/frame in a worker)"
+        % (frames, cores, wall, float(np.median(per))))
+    das_luts = OF.das_tables(w)
+    med = lambda runs: {k: round(float(np.median([r[k] for r in runs])), 4) for k in runs[0]}
+    stages = med([oracle_stages(ds, sel, luts, w, das_luts, das_stride=64) for _ in range(3)])
+    tw = C.TINY
+    tds = C.tiny_dataset(0)
+    tsel, tluts = OF.tables(tw)
+    tiny = med([oracle_stages(tds, tsel, tluts, tw, OF.das_tables(tw)) for _ in range(3)])
+    tiny_frame = sum(v for k, v in tiny.items() if k != "das")
+    return {
+        "value": round(frames * pixpair / wall / 1e9, 5),
+        "unit": "Gpixel·pair/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "%d whole vernier KK frames (decomposition + gather of both sets, FP64 numpy oracle), one frame per "
+                  "worker process at a time on %d forked workers: %.2f s wall = %.2f frames/s"
+                  % (frames, cores, wall, frames / wall),
+        "frames_per_s": round(frames / wall, 3),
+        "single_thread_stages_s_median_of_3": {
+            "vernier": stages, "vernier_das_note": "DAS on every 64th pixel, scaled to the whole grid",
+            "tiny": tiny, "tiny_frame_s": round(tiny_frame, 4),
+            "tiny_gpixel_pair_per_s": round(tw.X * tw.Z * len(tsel["pairs"]) / tiny_frame / 1e9, 5)},
+        "affinity_cores": len(os.sched_getaffinity(0)),
+        "cpu": cpu_model(),
+    }
 
 
 def cpu_model():
@@ -226,16 +304,17 @@ def precision_report(kk, C, torch, np, args):
     timed and compared with the FP64 oracle (sampled pixels of the beamformed sets) and with the
     FP32 run (whole image)."""
     import oracle as O
+    from oracle import frame as OF
     w = C.LARGE
     ds = C.speckle_dataset(w, seed=3, n_scat=20_000)
     su = kk.make_setup(w, with_das=False)
     dev = torch.device("cuda", 0)
     rf, sh, pd = kk.to_device(ds.rf), kk.to_device(su.luts["shift"]), kk.to_device(su.plan)
-    R64 = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    sel_o, luts_o = OF.tables(w)                       # the oracle's own selection and tables
+    R64 = O.decompose(ds.rf, luts_o["shift"], luts_o["tpad"])
     rng = np.random.default_rng(1)
     xi, zi = rng.integers(0, w.X, 400), rng.integers(0, w.Z, 400)
-    ref = O.kk_beamform(R64, su.sel["pairs"], su.sel["S"], su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                        su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
+    ref = OF.kk_image(None, sel_o, luts_o, w.X, w.Z, pixels=(xi, zi), rf_theta=R64)
     out = {"workload": "large: 192 el, 75 tx in +-18 deg, 4096 samples, Eq.6 j=0,37 M=9 (%d pairs), %dx%d px"
                        % (len(su.sel["pairs"]), w.X, w.Z)}
     img32 = None
@@ -345,7 +424,7 @@ def ensemble_report(kk, C, torch, np, args):
                         rt=torch.empty((su.N, su.M, su.T), dtype=torch.complex64, device=dev),
                         img=torch.empty((i.S, i.X, i.Z), dtype=torch.complex64, device=dev),
                         inten=torch.empty((i.X, i.Z), dtype=torch.float32, device=dev),
-                        bws=torch.empty(bws, dtype=torch.uint8, device=dev) if bws else None, rf=E.frame_rf(f)))
+                        bws=torch.zeros(bws, dtype=torch.uint8, device=dev) if bws else None, rf=E.frame_rf(f)))
 
     def per_frame_loop():
         for d in per:
@@ -426,7 +505,7 @@ def completion_report(kk, C, torch, np, args):
     against the fully sampled 128-angle KK image (GPU FP32, all pixels; FP64 oracle at sampled
     pixels for two phantoms), with the trained weights committed in the package."""
     from paper_2603_22496_amd import completion as CP
-    import oracle as O
+    from oracle import frame as OF
     cs = CP.setup()
     d = CP.Device(cs)
     loaded = CP.load()
@@ -454,10 +533,8 @@ def completion_report(kk, C, torch, np, args):
             errs["completed_best_gain"].append(b)
         if e < 2 and not args.no_parity:   # the oracle checks the outputs; it produces none of them
             xi, zi = rng.integers(0, cs.w.X, 300), rng.integers(0, cs.w.Z, 300)
-            su = cs.full
-            R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
-            r64 = O.kk_beamform(R, su.sel["pairs"], 1, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                                su.luts["lut4"], su.luts["t0_q"], cs.w.X, cs.w.Z, pixels=(xi, zi))[0]
+            sel_o, luts_o = OF.tables(cs.w, scheme=C.SCHEME_FULL_UNIFORM, M=len(cs.full.sel["rx_theta"]), j_list=(0,))
+            r64 = OF.kk_image(ds.rf, sel_o, luts_o, cs.w.X, cs.w.Z, pixels=(xi, zi))[0]
             errs64["compressed_best_gain"].append(CP.scaled_error(comp[0, xi, zi], r64)[1])
             if done is not None:
                 errs64["completed"].append(CP.scaled_error(done[0, xi, zi], r64)[0])
@@ -494,6 +571,61 @@ def study_report(np):
     return out
 
 
+def full_bank_report(kk, C, torch, np, ds, img_vernier, args, log):
+    """The same channel data beamformed over the dense 128-angle receive bank (all 3968 pairs,
+    one set): one-stream frame time, and the vernier frame's coherent compound compared with the
+    fully sampled image (raw rel-L2, rel-L2 after the best complex gain, envelope correlation)."""
+    from oracle import frame as OF
+    w = C.FULL
+    su = kk.make_setup(w)
+    dev = torch.device("cuda", 0)
+    rf = kk.to_device(ds.rf)
+    shift, pd = kk.to_device(su.luts["shift"]), kk.to_device(su.plan)
+    rt = torch.empty((w.N, su.M, w.T), dtype=torch.complex64, device=dev)
+    ws = torch.empty(kk.decompose_workspace_bytes(su.geom, w.N, su.M, su.tpad), dtype=torch.uint8, device=dev)
+    img = torch.empty((1, w.X, w.Z), dtype=torch.complex64, device=dev)
+    inten = torch.empty((w.X, w.Z), dtype=torch.float32, device=dev)
+    bws = torch.zeros(max(1, kk.beamform_workspace_bytes(su.plan)), dtype=torch.uint8, device=dev)
+
+    def frame():
+        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
+        kk.beamform(rt, su.plan, pd, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT, ws=bws)
+
+    ms = timed(frame, max(10, args.steps // 4), 3, torch, repeats=2)
+    ms_dec = timed(lambda: kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws), max(10, args.steps // 4),
+                   3, torch, repeats=2)
+    frame()
+    torch.cuda.synchronize()
+    full = img.cpu().numpy()[0]
+    coh = img_vernier.sum(axis=0)
+    a = full.ravel().astype(np.complex128)
+    b = coh.ravel().astype(np.complex128)
+    gain = np.vdot(b, a) / np.vdot(b, b)
+    env_a, env_b = np.abs(a), np.abs(b)
+    ea, eb = env_a - env_a.mean(), env_b - env_b.mean()
+    P = len(su.sel["pairs"])
+    out = {
+        "workload": "128-angle uniform receive bank over +-16 deg, all %d pairs, one set, same data and grid" % P,
+        "frame_us_one_stream": round(ms * 1e3, 2), "decompose_us": round(ms_dec * 1e3, 2),
+        "frames_per_s": round(1e3 / ms, 1), "gpixel_pair_per_s": round(w.X * w.Z * P / (ms * 1e-3) / 1e9, 1),
+        "plan_split": int(su.plan[24]),
+        "vernier_vs_full": {
+            "rel_l2": round(float(np.linalg.norm(b - a) / np.linalg.norm(a)), 4),
+            "rel_l2_after_best_complex_gain": round(float(np.linalg.norm(gain * b - a) / np.linalg.norm(a)), 4),
+            "envelope_correlation": round(float(np.dot(ea, eb) / np.sqrt(np.dot(ea, ea) * np.dot(eb, eb))), 4),
+            "compression": round(float(C.VERNIER.L / 14.0), 2)},
+    }
+    if not args.no_parity:
+        sel, luts = OF.tables(w)
+        rng = np.random.default_rng(3)
+        xi, zi = rng.integers(0, w.X, 200), rng.integers(0, w.Z, 200)
+        ref = OF.kk_image(ds.rf, sel, luts, w.X, w.Z, pixels=(xi, zi))[0]
+        out["rel_l2_vs_fp64_oracle_sampled"] = float(np.linalg.norm(full[xi, zi] - ref) / np.linalg.norm(ref))
+    log("full bank: %.2f us/frame (decompose %.2f us), vernier vs full %s"
+        % (ms * 1e3, ms_dec * 1e3, json.dumps(out["vernier_vs_full"])))
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -504,21 +636,29 @@ def main():
     import torch
 
     from paper_2603_22496_amd import configs as C
-    from paper_2603_22496_amd import kk
 
+    def log(msg):
+        print("bench: " + msg, file=sys.stderr, flush=True)
+
+    w = C.VERNIER
+    t0 = time.time()
+    ds = C.speckle_dataset(w, seed=2, n_scat=100_000)
+    log("vernier data generated in %.1fs" % (time.time() - t0))
+    # the CPU baseline first: its workers are forks of this process before it touches the GPU
+    cpu = cpu_baseline(C, ds, w, args.cpu_frames, log) if args.cpu_frames > 0 else None
+
+    from paper_2603_22496_amd import kk
     if not os.path.exists(kk.LIB_PATH):
         from paper_2603_22496_amd.build import build_all
         build_all()
     torch.cuda.set_device(0)
-    w = C.VERNIER
     t0 = time.time()
-    ds = C.speckle_dataset(w, seed=2, n_scat=100_000)
     su = kk.make_setup(w, with_das=not args.no_das)
     t_setup = time.time() - t0
     P = len(su.sel["pairs"])
     S = su.sel["S"]
-    print("bench: workload vernier N=%d L=%d T=%d M=%d P=%d S=%d grid %dx%d tpad=%d (setup %.1fs)"
-          % (w.N, w.L, w.T, su.M, P, S, w.X, w.Z, su.tpad, t_setup), file=sys.stderr, flush=True)
+    log("workload vernier N=%d L=%d T=%d M=%d P=%d S=%d grid %dx%d tpad=%d (setup %.1fs)"
+        % (w.N, w.L, w.T, su.M, P, S, w.X, w.Z, su.tpad, t_setup))
 
     dev = torch.device("cuda", 0)
     rf = kk.to_device(ds.rf)
@@ -528,7 +668,7 @@ def main():
     ws = torch.empty(kk.decompose_workspace_bytes(su.geom, w.N, su.M, su.tpad), dtype=torch.uint8, device=dev)
     img = torch.empty((S, w.X, w.Z), dtype=torch.complex64, device=dev)
     inten = torch.empty((w.X, w.Z), dtype=torch.float32, device=dev)
-    bws = torch.empty(max(1, kk.beamform_workspace_bytes(su.plan)), dtype=torch.uint8, device=dev)
+    bws = torch.zeros(max(1, kk.beamform_workspace_bytes(su.plan)), dtype=torch.uint8, device=dev)
 
     def frame():
         kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
@@ -538,19 +678,23 @@ def main():
         kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
 
     def gather_only():
-        kk.beamform(rt, su.plan, plan_dev, image=img, ws=bws)
+        kk.beamform(rt, su.plan, plan_dev, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT, ws=bws)
 
     # The timed region: K frames bracketed by synchronisation, frame k on stream k mod F with its
-    # own output and workspace buffers (F frames in flight; the channel data, tables and plan are
-    # shared read-only), as a scanner's stream of independent frames runs.
+    # own channel data (each stream's records are those of the phantom rotated in time by a
+    # different number of samples, so no stream re-reads another's input from the caches),
+    # outputs and workspaces; the tables and plan are shared read-only, as a scanner's stream
+    # of independent frames runs.
     nstreams = max(1, args.streams)
     streams = [torch.cuda.Stream() for _ in range(nstreams)]
-    bufs = [dict(rt=rt, ws=ws, img=img, inten=inten, bws=bws)]
-    for _ in range(nstreams - 1):
-        bufs.append({k: torch.empty_like(v) for k, v in bufs[0].items()})
+    bufs = [dict(rf=rf, rt=rt, ws=ws, img=img, inten=inten, bws=bws)]
+    for k in range(1, nstreams):
+        b = {key: torch.empty_like(v) for key, v in bufs[0].items() if key != "rf"}
+        b["rf"] = torch.roll(rf, shifts=97 * k, dims=2).contiguous()
+        bufs.append(b)
 
     def frame_on(b, st):
-        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=b["rt"], ws=b["ws"], stream=st)
+        kk.decompose(b["rf"], su.geom, shift, su.M, su.tpad, out=b["rt"], ws=b["ws"], stream=st)
         kk.beamform(b["rt"], su.plan, plan_dev, image=b["img"], intensity=b["inten"], mode=kk.COMPOUND_INCOHERENT,
                     ws=b["bws"], stream=st)
 
@@ -581,17 +725,21 @@ def main():
     torch.cuda.synchronize()
     wall = time.time() - wall0
     ms = e0.elapsed_time(e1) / args.steps
-    print("bench: %d KK frames on %d streams in %.3fs wall, %.2f us/frame" % (args.steps, nstreams, wall, ms * 1e3),
-          file=sys.stderr, flush=True)
-    # every stream's last frame against the first stream's (same input, same kernels)
-    same_streams = all(torch.equal(b["img"], bufs[0]["img"]) and torch.equal(b["inten"], bufs[0]["inten"])
-                       for b in bufs[1:])
+    log("%d KK frames on %d streams in %.3fs wall, %.2f us/frame" % (args.steps, nstreams, wall, ms * 1e3))
+    # every stream's last frame against the same input's frame computed alone on one stream
+    streams_ok = True
+    for b in bufs:
+        chk = dict(rf=b["rf"], rt=torch.empty_like(rt), ws=torch.empty_like(ws), img=torch.empty_like(img),
+                   inten=torch.empty_like(inten), bws=torch.zeros_like(bws))
+        frame_on(chk, cur)
+        torch.cuda.synchronize()
+        streams_ok &= bool(torch.equal(chk["img"], b["img"])) and bool(torch.equal(chk["inten"], b["inten"]))
     # one frame at a time on one stream (frame latency)
     ms_single = timed(frame, args.steps, 5, torch, repeats=2)
-    print("bench: one stream %.2f us/frame" % (ms_single * 1e3), file=sys.stderr, flush=True)
+    log("one stream %.2f us/frame" % (ms_single * 1e3))
 
     graph_rep = graph_report(frame, img, inten, args, torch, np)
-    print("bench: graph replay %s" % json.dumps(graph_rep), file=sys.stderr, flush=True)
+    log("graph replay %s" % json.dumps(graph_rep))
 
     ms_dec = timed(decompose_only, args.steps, 5, torch, repeats=3)
     ms_gather = timed(gather_only, args.steps, 5, torch, repeats=3)
@@ -599,12 +747,12 @@ def main():
     if not args.no_das:
         das_dev = kk.to_device(su.das_plan)
         dimg = torch.empty((w.X, w.Z), dtype=torch.complex64, device=dev)
-        dws = torch.empty(kk.das_workspace_bytes(su.geom, w.N, su.das_plan), dtype=torch.uint8, device=dev)
+        dws = torch.zeros(kk.das_workspace_bytes(su.geom, w.N, su.das_plan), dtype=torch.uint8, device=dev)
         das_steps = max(10, args.steps // 4)
         ms_das = timed(lambda: kk.das_beamform(rf, su.geom, su.das_plan, das_dev, image=dimg, ws=dws),
                        das_steps, 3, torch, repeats=2)
         res["das_ms"] = ms_das
-        print("bench: DAS %.2f us/frame" % (ms_das * 1e3), file=sys.stderr, flush=True)
+        log("DAS %.2f us/frame" % (ms_das * 1e3))
 
     def section(name, fn):
         """An extra report: a Python-level failure in it is recorded in the JSON line instead of
@@ -614,8 +762,14 @@ def main():
         except Exception as exc:
             import traceback
             traceback.print_exc()
-            print("bench: %s section failed: %s" % (name, exc), file=sys.stderr, flush=True)
+            log("%s section failed: %s" % (name, exc))
             return {"error": "%s: %s" % (type(exc).__name__, exc)}
+
+    frame()
+    torch.cuda.synchronize()
+    img_host = img.cpu().numpy()
+    if not args.no_full_bank:
+        res["full"] = section("full bank", lambda: full_bank_report(kk, C, torch, np, ds, img_host, args, log))
 
     if not args.no_precision:
         res["precision"] = section("precision", lambda: precision_report(kk, C, torch, np, args))
@@ -626,8 +780,7 @@ def main():
     if not args.no_completion:
         res["completion"] = section("completion", lambda: completion_report(kk, C, torch, np, args))
         if "error" not in res["completion"]:
-            print("bench: completion %s" % json.dumps(res["completion"]["rel_l2_vs_fully_sampled_gpu"]),
-                  file=sys.stderr, flush=True)
+            log("completion %s" % json.dumps(res["completion"]["rel_l2_vs_fully_sampled_gpu"]))
 
     if not args.no_study:
         res["study"] = section("study", lambda: study_report(np))
@@ -638,20 +791,20 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    # parity of this very frame against the FP64 oracle at sampled pixels (the oracle is
-    # test infrastructure: it checks the timed output, it never produces it)
-    import oracle as O
+    # parity of this very frame against the FP64 oracle at sampled pixels, the oracle using its
+    # own selection and tables (the oracle is test infrastructure: it checks the timed output,
+    # it never produces it)
     rel = None
-    if not args.no_parity or args.cpu_frames > 0:
-        frame()
-        torch.cuda.synchronize()
-        got = img.cpu().numpy()
-        R = O.decompose(ds.rf, su.luts["shift"], su.tpad)
+    if not args.no_parity:
+        from oracle import frame as OF
+        sel_o, luts_o = OF.tables(w)
+        assert np.array_equal(np.asarray(sel_o["pairs"]), su.sel["pairs"])
+        for key in ("lut1", "lut2", "lut3", "lut4", "shift"):
+            assert np.array_equal(luts_o[key], su.luts[key]), key
         rng = np.random.default_rng(0)
         xi, zi = rng.integers(0, w.X, 500), rng.integers(0, w.Z, 500)
-        ref = O.kk_beamform(R, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                            su.luts["lut4"], su.luts["t0_q"], w.X, w.Z, pixels=(xi, zi))
-        rel = float(np.linalg.norm(got[:, xi, zi] - ref) / np.linalg.norm(ref))
+        ref = OF.kk_image(ds.rf, sel_o, luts_o, w.X, w.Z, pixels=(xi, zi))
+        rel = float(np.linalg.norm(img_host[:, xi, zi] - ref) / np.linalg.norm(ref))
 
     pixpair = w.X * w.Z * P
     gather_rate = pixpair / (ms_gather * 1e-3)
@@ -667,15 +820,18 @@ def main():
     dec_fused = rec_bytes + rt_bytes
     dec_flops = 8.0 * su.M * w.L * w.N * K
     t_dec = ms_dec * 1e-3
+    t_dec_bound = dec_unfused / HBM_BYTES_PER_S
+    t_gather_bound = OPS_PER_PIXEL_PAIR * pixpair / VALU_LANE_OPS
     stage_roofs = {
         "decompose": {"bound": "hbm", "time_us": round(ms_dec * 1e3, 2),
-                      "bytes_unfused": dec_unfused, "frac_unfused": round(dec_unfused / HBM_BYTES_PER_S / t_dec, 4),
+                      "bytes_unfused": dec_unfused, "frac_unfused": round(t_dec_bound / t_dec, 4),
                       "bytes_fused_minimum": dec_fused,
                       "frac_fused_minimum": round(dec_fused / HBM_BYTES_PER_S / t_dec, 4),
                       "mfma_flops": dec_flops, "frac_mfma": round(dec_flops / MFMA_FP32_FLOPS / t_dec, 4)},
         "beamform": {"bound": "alu", "time_us": round(ms_gather * 1e3, 2),
                      "lane_ops": OPS_PER_PIXEL_PAIR * pixpair,
-                     "frac": round(OPS_PER_PIXEL_PAIR * pixpair / VALU_LANE_OPS / (ms_gather * 1e-3), 4)},
+                     "frac": round(t_gather_bound / (ms_gather * 1e-3), 4),
+                     "note": "gather kernel alone; the Eq. 9 intensity of the sets follows in a separate pass"},
     }
     out = {
         "metric": METRIC,
@@ -697,7 +853,7 @@ def main():
         },
         "frames_per_s": round(1e3 / ms, 1),
         "streams": nstreams,
-        "streams_identical": same_streams,
+        "streams_match_single_frames": streams_ok,
         "stages_us": {"decompose": round(ms_dec * 1e3, 2), "gather": round(ms_gather * 1e3, 2),
                       "frame": round(ms * 1e3, 2), "frame_one_stream": round(ms_single * 1e3, 2)},
         "beamform_gpixpair_per_s": round(gather_rate / 1e9, 1),
@@ -713,47 +869,32 @@ def main():
             "ops_per_pixel_pair": OPS_PER_PIXEL_PAIR,
             "pixel_pairs_per_launch": pixpair,
         },
+        # the whole frame against the sum of its stages' bounds (decomposition at its unfused HBM
+        # bound, gather at its VALU bound), for the timed loop and for one frame at a time
+        "frame_roofline": {"bound_us": round((t_dec_bound + t_gather_bound) * 1e6, 2),
+                           "frac_timed_loop": round((t_dec_bound + t_gather_bound) / (ms * 1e-3), 4),
+                           "frac_one_stream": round((t_dec_bound + t_gather_bound) / (ms_single * 1e-3), 4)},
         "stage_rooflines": stage_roofs,
         "graph": graph_rep,
         "clocks": gpu_clocks(),
     }
-    if "precision" in res:
-        out["precision_large"] = res["precision"]
-    if "ensemble" in res:
-        out["ensemble"] = res["ensemble"]
-    if "completion" in res:
-        out["completion"] = res["completion"]
-    if "study" in res:
-        out["study"] = res["study"]
+    for key, name in (("full", "full_bank"), ("precision", "precision_large"), ("ensemble", "ensemble"),
+                      ("completion", "completion"), ("study", "study")):
+        if key in res:
+            out[name] = res[key]
     if "das_ms" in res:
         das_units = w.X * w.Z * w.N * w.L                 # pixel x (transmit, element) gathers
+        das_frac = round(OPS_PER_PIXEL_PAIR * das_units / VALU_LANE_OPS / (res["das_ms"] * 1e-3), 4)
         out["stage_rooflines"]["das"] = {
             "bound": "alu", "time_us": round(res["das_ms"] * 1e3, 2), "lane_ops": OPS_PER_PIXEL_PAIR * das_units,
-            "frac": round(OPS_PER_PIXEL_PAIR * das_units / VALU_LANE_OPS / (res["das_ms"] * 1e-3), 4)}
+            "frac": das_frac, "note": "analytic transforms and the DAS gather, against the gather's VALU bound"}
         out["das_frames_per_s"] = round(1e3 / res["das_ms"], 1)
         out["stages_us"]["das"] = round(res["das_ms"] * 1e3, 2)
         out["kk_over_das_speedup"] = round(res["das_ms"] / ms_single, 2)   # both one frame at a time
-
-    if args.cpu_frames > 0:
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):
-            t = time.time()
-            for _ in range(args.cpu_frames):
-                Rc = O.decompose(ds.rf, su.luts["shift"], su.tpad)
-                O.kk_beamform(Rc, su.sel["pairs"], S, su.luts["lut1"], su.luts["lut2"], su.luts["lut3"],
-                              su.luts["lut4"], su.luts["t0_q"], w.X, w.Z)
-            dt = (time.time() - t) / args.cpu_frames
-            stages = oracle_stage_seconds(O, ds, su, S, w)
-        out["cpu_baseline"] = {
-            "value": round(pixpair / dt / 1e9, 5),
-            "unit": "Gpixel·pair/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": "%d full vernier KK frames (decompose + beamform, FP64 numpy), %.2f s/frame = %.3f frames/s"
-                      % (args.cpu_frames, dt, 1.0 / dt),
-            "stages_s": stages,
-            "cpu": cpu_model(),
-        }
+        out["kk_over_das_context"] = {"kk_gather_frac": stage_roofs["beamform"]["frac"], "das_frac": das_frac,
+                                      "pair_ratio": round(w.N * w.L / P, 2)}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -414,6 +414,10 @@ __global__ void fill_zero_kernel(int32_t* __restrict__ p, int n) {
     if (i < n) p[i] = 0;
 }
 
+// |v|^2 with one fixed rounding sequence, so that every intensity of the library (the gather's
+// share reduction and kk_compound) agrees bit for bit.
+__device__ __forceinline__ float norm2(float2 v) { return __builtin_fmaf(v.x, v.x, v.y * v.y); }
+
 // Sum of the K pair shares of each set (fixed order), written as the per-set images, and the
 // Eq. 8 / Eq. 9 intensity of the set images when requested.
 __device__ __forceinline__ void reduce_body(const float2* __restrict__ part, int K, int S, int npix,
@@ -431,9 +435,9 @@ __device__ __forceinline__ void reduce_body(const float2* __restrict__ part, int
         if (image) image[(size_t)s * npix + i] = v;
         coh.x += v.x;
         coh.y += v.y;
-        inc += v.x * v.x + v.y * v.y;
+        inc += norm2(v);
     }
-    if (inten) inten[i] = (mode == KK_COMPOUND_COHERENT) ? coh.x * coh.x + coh.y * coh.y : inc;
+    if (inten) inten[i] = (mode == KK_COMPOUND_COHERENT) ? norm2(coh) : inc;
 }
 
 __global__ void reduce_kernel(const float2* __restrict__ part, int K, int S, int npix, float2* __restrict__ image,

@@ -28,20 +28,20 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kContractWaves = kBinBlock;   // one bin of the block per wave
+// Contraction workgroup: one block of 8 bins, 16 receive angles, 32 transmit columns; wave w
+// takes the bin pair p = w % 4 (bins 8 kb + 2p, 8 kb + 2p + 1) over half h = w / 4 of the
+// elements, and the two halves are summed at the end.
+constexpr int kContractWaves = 8;
 constexpr int kContractThreads = kContractWaves * 64;
-constexpr int kChunkL = 16;                  // elements per LDS chunk
-// One transmit column of a chunk plus a pad of two floats: rows stay 8-byte aligned and
-// column c's operand reads land on banks 2c, 2c+1, so a wave's 32 columns x {Re, Im} hit all
-// 64 banks once.
-constexpr int kRowFloats = kChunkL * kBinBlock * 2 + 2;
-// Chunks whose global loads are in flight.  Two measure faster than four or eight: the loop is
-// bound by LDS traffic and barriers rather than by load latency, and fewer register stages
-// leave fewer zero chunks at the end of a ragged element count.
-constexpr int kStages = 2;
-// Phases of one element of a chunk: 8 bins x 16 angles, then a pad of 16 (288 words, 32 modulo
-// the 64 banks): the phase stores of a wave (two elements per 32-lane half) cover every bank once.
-constexpr int kWsL = kBinBlock * 16 + 16;
+// Elements whose anchor phases W_{8 kb}[o][l] sit in LDS at once.
+constexpr int kAnchorChunk = 256;
+// Elements whose operand loads are in flight per wave.
+constexpr int kDepth = 8;
+// Result staging per transmit column: 16 angles x 8 bins and a pad (a half-wave's 32 columns
+// then write 64 distinct banks).
+constexpr int kYCol = 16 * kBinBlock + 1;
+constexpr int kBufFloat2 = 32 * kYCol;  // >= anchors (kAnchorChunk x 16) and the half sums (4096)
+static_assert(kBufFloat2 >= kAnchorChunk * 16 && kBufFloat2 >= 4096, "LDS buffer");
 
 // exp(+2 pi i ((k s) mod (n 2^22)) / (n 2^22)) for 0 <= k < 2^23, any int32 s: the turn count
 // is reduced exactly with 24-bit products (k s = k s_hi 2^22 + k s_lo, s_lo < 2^22), the coarse
@@ -80,152 +80,156 @@ __device__ __forceinline__ void build_phase_factors(float2* fac, int tid) {
     }
 }
 
-// Global loads of one chunk: spectrum X[kb][i][l0 .. l0+15][0..7] (a contiguous 1 KiB run per
-// transmit column i) and the shift of this thread's (receive angle, element) entry.
-struct ContractStage {
-    float4 v[4];
-    int32_t s;
-};
-
-// Every path issues the same loads (clamped to valid addresses; out-of-range entries are
-// zeroed at the store), so the wait before a stage's store can leave the later stages in flight.
-__device__ __forceinline__ void contract_load(ContractStage& st, const float2* __restrict__ X,
-                                              const int32_t* __restrict__ shift, int kb, int ncol, int ct, int L,
-                                              int l0, int M, int rt, int tid) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * kContractThreads;  // float4 index in the 32 x 64 chunk
-        const int i = f >> 6, j = f & 63;          // column, float4 within the column's run
-        const int l = min(l0 + (j >> 2), L - 1);
-        st.v[u] = reinterpret_cast<const float4*>(X + (((size_t)kb * ncol + ct * 32 + i) * L + l) * kBinBlock)[j & 3];
-    }
-    const int o = min(rt * 16 + (tid & 15), M - 1), l = min(l0 + ((tid >> 4) & 15), L - 1);
-    st.s = shift[(size_t)o * L + l];  // used by threads 0..255, (angle, element) = (tid % 16, tid / 16)
-}
-
-// Spectrum rows into LDS, and the phases W[l][bin][angle] of the chunk: thread (angle, l) of
-// the first four waves evaluates the phase of the block's first bin exactly and the one-bin
-// step D = exp(2 pi i s / (n 2^22)), and forms the other seven bins as products of D, D^2 and
-// D^4 (at most five roundings deep).
+// Anchor phases of elements [c0, c0 + cn) of one bin block and receive tile:
+// anc[(l - c0) 16 + o % 16] = W_{8 kb}[o][l] (zero for o >= M), evaluated exactly.
 template <int LOG2N>
-__device__ __forceinline__ void contract_store(const ContractStage& st, float* xs, float2* ws, const float2* fac,
-                                               int kb, int l0, int L, int M, int rt, int tid) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * kContractThreads;
-        const int i = f >> 6, j = f & 63;
-        const bool in = l0 + (j >> 2) < L;
-        float2* row = reinterpret_cast<float2*>(xs + i * kRowFloats + j * 4);
-        row[0] = in ? make_float2(st.v[u].x, st.v[u].y) : make_float2(0.f, 0.f);
-        row[1] = in ? make_float2(st.v[u].z, st.v[u].w) : make_float2(0.f, 0.f);
-    }
-    if (tid < 256) {  // waves 0..3
-        const int ol = tid & 15, ll = tid >> 4;
-        const bool valid = rt * 16 + ol < M && l0 + ll < L;
-        const float2 w0 = shear_phase<LOG2N>((uint32_t)(kb * kBinBlock), st.s, fac);
-        const float2 d1 = shear_phase<LOG2N>(1u, st.s, fac);
-        const float2 d2 = cmul2(d1, d1), d4 = cmul2(d2, d2);
-        const float2 w1 = cmul2(w0, d1), w2 = cmul2(w0, d2), w3 = cmul2(w1, d2);
-        const float2 w[8] = {w0, w1, w2, w3, cmul2(w0, d4), cmul2(w1, d4), cmul2(w2, d4), cmul2(w3, d4)};
-        const float2 zero = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int b = 0; b < kBinBlock; ++b) ws[ll * kWsL + b * 16 + ol] = valid ? w[b] : zero;
+__device__ __forceinline__ void build_anchors(float2* anc, const float2* fac, const int32_t* __restrict__ shift,
+                                              int kb, int rt, int M, int L, int c0, int cn, int tid) {
+    for (int e = tid; e < cn * 16; e += kContractThreads) {
+        const int o = rt * 16 + (e & 15), l = c0 + (e >> 4);
+        anc[e] = o < M ? shear_phase<LOG2N>((uint32_t)(kb * kBinBlock), shift[(size_t)o * L + l], fac)
+                       : make_float2(0.f, 0.f);
     }
 }
 
-// MFMA operands of one chunk for one lane: the spectrum value (B) and the phase component (A,
-// sign applied) of each of the chunk's 16 elements.
-struct ChunkOperands {
-    float a[kChunkL];
-    float b[kChunkL];
+// Lane roles of v_mfma_f32_32x32x2_f32.  A (32 x 2): row lane % 32 = {Re rows 0..15, Im rows
+// 16..31} x 16 receive angles, column lane / 32 = {Re, Im} part of the element; the lane
+// supplies Wr (Re row, Re part), -Wi (Re row, Im part), Wi (Im row, Re part), Wr (Im, Im).
+// B (2 x 32): part lane / 32 of transmit column lane % 32.
+struct LaneRole {
+    int part, col, orow;
+    bool use_im;
+    uint32_t negmask;
+    __device__ __forceinline__ explicit LaneRole(int lane) {
+        part = lane >> 5;
+        col = lane & 31;
+        orow = col & 15;
+        const int ytype = col >> 4;
+        use_im = ytype != part;
+        negmask = (ytype == 0 && part == 1) ? 0x80000000u : 0u;
+    }
+    __device__ __forceinline__ float pick(float2 w) const {
+        return __uint_as_float(__float_as_uint(use_im ? w.y : w.x) ^ negmask);
+    }
 };
 
-__device__ __forceinline__ void read_operands(ChunkOperands& op, const float* xs, const float2* ws, int col, int wave,
-                                              int part, int orow, int comp, uint32_t negmask) {
-    const float* xrow = xs + col * kRowFloats + wave * 2 + part;
-    const float* wrow = reinterpret_cast<const float*>(ws) + (wave * 16 + orow) * 2 + comp;
-#pragma unroll
-    for (int ll = 0; ll < kChunkL; ++ll) {
-        op.b[ll] = xrow[ll * kBinBlock * 2];
-        op.a[ll] = __uint_as_float(__float_as_uint(wrow[ll * kWsL * 2]) ^ negmask);
-    }
-}
+// Operands of one element in flight: spectrum (bin 2p + part of this lane's transmit), anchor
+// phase of this lane's angle, phase steps {D_2p, D_1}.
+struct ElemLoads {
+    float2 x;
+    float2 a;
+    float4 d;
+};
 
-// the 16 MFMAs of one chunk, in two interleaved accumulation chains (even and odd elements)
-__device__ __forceinline__ void chunk_mfma(floatx16 (&acc)[2], const ChunkOperands& op) {
-#pragma unroll
-    for (int ll = 0; ll < kChunkL; ++ll)
-        acc[ll & 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(op.a[ll], op.b[ll], acc[ll & 1], 0, 0, 0);
-}
-
-// Per bin block (8 bins, one per wave), receive-angle tile of 16 and transmit tile of 32:
-// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] over all elements in chunks of 16.  Software pipeline
-// across chunks, one workgroup barrier per chunk: while the MFMAs of chunk c run from
-// registers, the operands of chunk c+1 are read from LDS and chunk c+2 (spectrum rows and its
-// phases) is written to LDS from its register stage, whose global loads were issued kStages
-// chunks earlier.  The results leave through LDS as 64-byte runs (8 bins of one (i, o)).
+// Per bin block (8 bins), receive tile of 16 and transmit tile of 32:
+// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i].  W_{8kb+2p} = W_{8kb} D_2p and W_{8kb+2p+1} =
+// W_{8kb+2p} D_1 (two roundings from exactly evaluated factors).  The spectrum is read
+// straight from global memory: one 8-byte load per lane gives bins 2p (lanes 0..31 Re, 32..63
+// Im after one v_permlane32_swap) and 2p+1; no LDS staging and no barrier in the element loop.
+// Results leave through LDS as 64-byte runs (8 bins of one (i, o)).
 template <int LOG2N>
 __device__ __forceinline__ void contract_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
-                                              float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad,
-                                              int kb, int rt, int ct) {
+                                              const float4* __restrict__ phd, float2* __restrict__ Y, int ntx,
+                                              int M, int L, int ncol, int kpad, int kb, int rt, int ct) {
     constexpr int N = 1 << LOG2N;
     __shared__ float2 fac[64 + N / 64];
-    __shared__ __attribute__((aligned(16))) float xs[2][32 * kRowFloats];
-    __shared__ float2 ws[2][kChunkL * kWsL];                      // [l][bin][angle] (+ pad per l)
+    __shared__ __attribute__((aligned(16))) float2 buf[kBufFloat2];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int p = wave & 3, h = wave >> 2;
+    const LaneRole R(lane);
     build_phase_factors<LOG2N>(fac, tid);
-    // lane roles.  B (2 x 32): part = lane / 32 in {Re, Im}, transmit column lane % 32.
-    // A (32 x 2): row lane % 32 = {Re rows 0..15, Im rows 16..31} x 16 receive angles; the lane
-    // supplies Wr (Re row, Re part), -Wi (Re row, Im part), Wi (Im row, Re part), Wr (Im, Im).
-    const int part = lane >> 5;
-    const int col = lane & 31;
-    const int ytype = col >> 4;
-    const int orow = col & 15;
-    const int comp = (ytype == part) ? 0 : 1;
-    const uint32_t negmask = (ytype == 0 && part == 1) ? 0x80000000u : 0u;
 
-    floatx16 acc[2];
+    floatx16 acc0, acc1;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[0][v] = acc[1][v] = 0.0f;
+    for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
 
-    // a whole number of pipeline rounds: chunks past the last element are all zero
-    const int nchunks = (L + kChunkL * kStages - 1) / (kChunkL * kStages) * kStages;
-    ContractStage st[kStages];
-    ChunkOperands op[2];
+    // element l of this lane's operands: spectrum X[spec_index(8 kb + 2p + part, l, 32 ct + col)],
+    // phase steps PhD[((rt 4 + p) L + l) 16 + orow]
+    const size_t xstride = (size_t)kBinBlock * ncol;
+    // padding columns past the last transmit (never written) read the last transmit's spectrum,
+    // whose lines are fetched anyway; their results are discarded
+    const int icol = min(ct * 32 + R.col, ntx - 1);
+    const float2* xp = X + spec_index(kb * kBinBlock + 2 * p, 0, icol, L, ncol) + R.part;
+    const float4* dp = phd + ((size_t)rt * 4 + p) * L * 16 + R.orow;
+
+    for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
+        const int cn = min(kAnchorChunk, L - c0);
+        __syncthreads();  // factor tables complete; the previous chunk's anchors consumed
+        build_anchors<LOG2N>(buf, fac, shift, kb, rt, M, L, c0, cn, tid);
+        __syncthreads();
+        const int half = (cn + 1) >> 1;
+        const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
+        const int e1 = __builtin_amdgcn_readfirstlane(min(c0 + cn, e0 + half));
+        if (e0 < e1) {
+            // a whole number of kDepth-element steps; elements past the last one re-read it
+            // and enter with a zero phase
+            const int last = e1 - 1;
+            const int steps = (e1 - e0 + kDepth - 1) / kDepth;
+            ElemLoads q[kDepth];
 #pragma unroll
-    for (int u = 0; u < kStages; ++u) contract_load(st[u], X, shift, kb, ncol, ct, L, u * kChunkL, M, rt, tid);
-    __syncthreads();  // phase factors complete
-    contract_store<LOG2N>(st[0], xs[0], ws[0], fac, kb, 0, L, M, rt, tid);
-    contract_load(st[0], X, shift, kb, ncol, ct, L, kStages * kChunkL, M, rt, tid);
-    contract_store<LOG2N>(st[1], xs[1], ws[1], fac, kb, kChunkL, L, M, rt, tid);
-    contract_load(st[1], X, shift, kb, ncol, ct, L, (kStages + 1) * kChunkL, M, rt, tid);
-    __syncthreads();
-    read_operands(op[0], xs[0], ws[0], col, wave, part, orow, comp, negmask);
-    __syncthreads();  // every wave has chunk 0's operands before buffer 0 takes chunk 2
-    for (int c0 = 0; c0 < nchunks; c0 += kStages) {
+            for (int u = 0; u < kDepth; ++u) {
+                const int l = min(e0 + u, last);
+                q[u].x = xp[(size_t)l * xstride];
+                q[u].d = dp[(size_t)l * 16];
+                q[u].a = buf[(l - c0) * 16 + R.orow];
+                asm volatile("" ::: "memory");  // the prologue issues its loads in the loop's order
+            }
+            int e = e0;
+            for (int it = 0; it < steps; ++it, e += kDepth) {
 #pragma unroll
-        for (int u = 0; u < kStages; ++u) {
-            const int c = c0 + u;  // chunk c: operands in op[u & 1]; c+1 in LDS buffer (u+1)&1
-            chunk_mfma(acc, op[u & 1]);
-            read_operands(op[(u + 1) & 1], xs[(u + 1) & 1], ws[(u + 1) & 1], col, wave, part, orow, comp, negmask);
-            const int s2 = (u + 2) % kStages;  // register stage of chunk c+2 (static once unrolled)
-            // chunk c+2 over chunk c's LDS buffer (read before the previous barrier), then the
-            // freed stage takes chunk c+2+kStages (loads past the end re-read valid addresses)
-            contract_store<LOG2N>(st[s2], xs[u & 1], ws[u & 1], fac, kb, (c + 2) * kChunkL, L, M, rt, tid);
-            contract_load(st[s2], X, shift, kb, ncol, ct, L, (c + 2 + kStages) * kChunkL, M, rt, tid);
-            __syncthreads();
+                for (int u = 0; u < kDepth; ++u) {
+                    // operands of element e + u from the buffer ...
+                    const ElemLoads& c = q[u];
+                    const float2 an = e + u <= last ? c.a : make_float2(0.f, 0.f);
+                    const auto sw =
+                        __builtin_amdgcn_permlane32_swap(__float_as_uint(c.x.x), __float_as_uint(c.x.y), false, false);
+                    const float2 w0 = cmul2(an, make_float2(c.d.x, c.d.y));
+                    const float2 w1 = cmul2(w0, make_float2(c.d.z, c.d.w));
+                    const float a0 = R.pick(w0), a1 = R.pick(w1);
+                    // ... then the buffer takes the element kDepth ahead (into the same registers;
+                    // the spectrum after the products that read its swapped copy)
+                    const int ln = min(e + u + kDepth, last);
+                    q[u].d = dp[(size_t)ln * 16];
+                    q[u].a = buf[(ln - c0) * 16 + R.orow];
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, __uint_as_float(sw[0]), acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, __uint_as_float(sw[1]), acc1, 0, 0, 0);
+                    q[u].x = xp[(size_t)ln * xstride];
+                    // keeps each element's refill loads in its own step (the loads stay kDepth
+                    // steps ahead of their use instead of being moved next to it)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
         }
     }
-    // results to LDS as runs [i][o][bin] (i stride 129 float2, so a half-wave's 32 columns
-    // write 64 distinct banks), then out as 64-byte runs, 8 threads per run
-    constexpr int kYCol = 16 * kBinBlock + 1;
-    static_assert(32 * kYCol * 8 <= (int)sizeof(xs), "result staging fits the spectrum buffers");
-    float2* yst = reinterpret_cast<float2*>(&xs[0][0]);
+    // the element halves: waves 4..7 hand their sums to waves 0..3 through LDS
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(buf);
+    if (h == 1) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        yst[col * kYCol + ol * kBinBlock + wave] = make_float2(acc[0][v] + acc[1][v], acc[0][v + 8] + acc[1][v + 8]);
+        for (int v = 0; v < 16; ++v) {
+            red[((p * 2 + 0) * 16 + v) * 64 + lane] = acc0[v];
+            red[((p * 2 + 1) * 16 + v) * 64 + lane] = acc1[v];
+        }
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            acc0[v] += red[((p * 2 + 0) * 16 + v) * 64 + lane];
+            acc1[v] += red[((p * 2 + 1) * 16 + v) * 64 + lane];
+        }
+    }
+    __syncthreads();
+    // results to LDS as runs [i][o][bin], then out as 64-byte runs, 8 threads per run
+    float2* yst = buf;
+    if (h == 0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+            yst[R.col * kYCol + ol * kBinBlock + 2 * p] = make_float2(acc0[v], acc0[v + 8]);
+            yst[R.col * kYCol + ol * kBinBlock + 2 * p + 1] = make_float2(acc1[v], acc1[v + 8]);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -241,17 +245,16 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
 // ---------------------------------------------------------------------------------------
 // Split-precision contraction: the same per-bin product with 16-bit MFMA inputs.  Every
 // spectrum value and phase is split as x = hi + lo, hi = round16(x), lo = round16(x - hi)
-// (BF16 or FP16), and Y = Wh Xh + Wh Xl + Wl Xh accumulated in FP32 on
-// v_mfma_f32_32x32x16_{bf16,f16} (eight complex elements per instruction: K = {Re, Im} x 8).
-// The dropped Wl Xl term and the residuals are below 2^-16 (BF16) or 2^-22 (FP16) of the
-// terms.  FP16 spectra are first scaled by 2^e so that |X| < 2^15 (|X| <= 2 T 32768 for int16
-// records), and Y by 2^-e (both exact).
+// (BF16 or FP16), and Y = Wh Xl + Wl Xh + Wh Xh accumulated in FP32 on
+// v_mfma_f32_32x32x16_{bf16,f16} (eight complex elements per instruction: K = 8 elements x
+// {Re, Im}; lane l holds K slice 8 (l / 32) .. + 7, i.e. elements 4 (l / 32) .. + 3, of row or
+// column l % 32).  The dropped Wl Xl term and the residuals are below 2^-16 (BF16) or 2^-22
+// (FP16) of the terms.  FP16 spectra are first scaled by 2^e so that |X| < 2^15 (|X| <= 2 T
+// 32768 for int16 records), and Y by 2^-e (both exact).  Same workgroup shape, spectrum
+// layout and phase construction as the FP32 kernel.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kXsWords = kBinBlock * 2 * kChunkL + 4;  // per column: [bin][hi, lo][l] + pad (16 B)
-constexpr int kWsBlock = 2 * kChunkL + 4;              // per (bin, angle, row type): [hi, lo][l] + pad
 
 template <bool F16>
 __device__ __forceinline__ uint32_t half_bits(float x) {
@@ -267,74 +270,12 @@ __device__ __forceinline__ float half_value(float x) {
     else
         return (float)(__bf16)x;
 }
-// (re, im) -> hi pair and lo pair, low half = re
+// (first, second) -> hi pair and lo pair, low half = first
 template <bool F16>
-__device__ __forceinline__ void split_pair(float re, float im, uint32_t& hi, uint32_t& lo) {
-    const float rh = half_value<F16>(re), ih = half_value<F16>(im);
-    hi = half_bits<F16>(re) | (half_bits<F16>(im) << 16);
-    lo = half_bits<F16>(re - rh) | (half_bits<F16>(im - ih) << 16);
-}
-
-template <int LOG2N, bool F16>
-__device__ __forceinline__ void split_store(const ContractStage& st, uint32_t* xs, uint32_t* ws, const float2* fac,
-                                            int kb, int l0, int L, int M, int rt, int tid, float xscale) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int f = tid + u * kContractThreads;
-        const int i = f >> 6, j = f & 63;        // column, float4 (two bins of one element)
-        const int l = j >> 2, q = j & 3;
-        const bool in = l0 + l < L;
-        const float v[4] = {st.v[u].x * xscale, st.v[u].y * xscale, st.v[u].z * xscale, st.v[u].w * xscale};
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            uint32_t hi, lo;
-            split_pair<F16>(v[2 * h], v[2 * h + 1], hi, lo);
-            uint32_t* d = xs + i * kXsWords + ((2 * q + h) * 2) * kChunkL + l;
-            d[0] = in ? hi : 0u;
-            d[kChunkL] = in ? lo : 0u;
-        }
-    }
-    if (tid < 256) {  // waves 0..3: phases of (angle, element) for the block's 8 bins
-        const int ol = tid & 15, ll = tid >> 4;
-        const bool valid = rt * 16 + ol < M && l0 + ll < L;
-        const float2 w0 = shear_phase<LOG2N>((uint32_t)(kb * kBinBlock), st.s, fac);
-        const float2 d1 = shear_phase<LOG2N>(1u, st.s, fac);
-        const float2 d2 = cmul2(d1, d1), d4 = cmul2(d2, d2);
-        const float2 w1 = cmul2(w0, d1), w2 = cmul2(w0, d2), w3 = cmul2(w1, d2);
-        const float2 w[8] = {w0, w1, w2, w3, cmul2(w0, d4), cmul2(w1, d4), cmul2(w2, d4), cmul2(w3, d4)};
-#pragma unroll
-        for (int b = 0; b < kBinBlock; ++b) {
-            uint32_t rh, rl, ih, il;
-            split_pair<F16>(w[b].x, -w[b].y, rh, rl);  // Re rows: (Wr, -Wi)
-            split_pair<F16>(w[b].y, w[b].x, ih, il);   // Im rows: (Wi, Wr)
-            uint32_t* dr = ws + ((b * 16 + ol) * 2 + 0) * kWsBlock + ll;
-            uint32_t* di = ws + ((b * 16 + ol) * 2 + 1) * kWsBlock + ll;
-            dr[0] = valid ? rh : 0u;
-            dr[kChunkL] = valid ? rl : 0u;
-            di[0] = valid ? ih : 0u;
-            di[kChunkL] = valid ? il : 0u;
-        }
-    }
-}
-
-// MFMA operands of one chunk: two K-steps of 8 elements, hi and lo of A (phases) and B (spectrum)
-struct SplitOperands {
-    u32x4 ah[2], al[2], bh[2], bl[2];
-};
-
-__device__ __forceinline__ void split_read(SplitOperands& op, const uint32_t* xs, const uint32_t* ws, int col, int g,
-                                           int wave) {
-    // B lane (g, col): elements 4g..4g+3 of K-step s for transmit col; A lane (g, row col):
-    // the same elements for row (angle col % 16, Re/Im col / 16)
-    const uint32_t* xb = xs + col * kXsWords + wave * 2 * kChunkL + 4 * g;
-    const uint32_t* wa = ws + ((wave * 16 + (col & 15)) * 2 + (col >> 4)) * kWsBlock + 4 * g;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        op.bh[s] = *reinterpret_cast<const u32x4*>(xb + 8 * s);
-        op.bl[s] = *reinterpret_cast<const u32x4*>(xb + kChunkL + 8 * s);
-        op.ah[s] = *reinterpret_cast<const u32x4*>(wa + 8 * s);
-        op.al[s] = *reinterpret_cast<const u32x4*>(wa + kChunkL + 8 * s);
-    }
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
+    const float ah = half_value<F16>(a), bh = half_value<F16>(b);
+    hi = half_bits<F16>(a) | (half_bits<F16>(b) << 16);
+    lo = half_bits<F16>(a - ah) | (half_bits<F16>(b - bh) << 16);
 }
 
 template <bool F16>
@@ -347,67 +288,134 @@ __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
                                                        c, 0, 0, 0);
 }
 
-template <bool F16>
-__device__ __forceinline__ void split_mfma(floatx16 (&acc)[2], const SplitOperands& op) {
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        acc[s] = mfma16<F16>(op.ah[s], op.bl[s], acc[s]);
-        acc[s] = mfma16<F16>(op.al[s], op.bh[s], acc[s]);
-        acc[s] = mfma16<F16>(op.ah[s], op.bh[s], acc[s]);
-    }
-}
+// Loads of one group of 8 elements for one lane: its 4 elements' spectra (bins 2p and 2p+1),
+// anchors and phase steps.
+struct SplitLoads {
+    float4 x[4];
+    float2 a[4];
+    float4 d[4];
+};
 
-// Same workgroup shape and software pipeline as contract_kernel.
 template <int LOG2N, bool F16>
 __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
-                                                    float2* __restrict__ Y, int ntx, int M, int L, int ncol,
-                                                    int kpad, float xscale, float yscale, int kb, int rt, int ct) {
+                                                    const float4* __restrict__ phd, float2* __restrict__ Y, int ntx,
+                                                    int M, int L, int ncol, int kpad, float xscale, float yscale,
+                                                    int kb, int rt, int ct) {
     constexpr int N = 1 << LOG2N;
     __shared__ float2 fac[64 + N / 64];
-    __shared__ __attribute__((aligned(16))) uint32_t xs[2][32 * kXsWords];
-    __shared__ __attribute__((aligned(16))) uint32_t ws[2][kBinBlock * 16 * 2 * kWsBlock];
+    __shared__ __attribute__((aligned(16))) float2 buf[kBufFloat2];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
+    const int p = wave & 3, h = wave >> 2;
+    const int g = lane >> 5, col = lane & 31, orow = col & 15;
+    const bool im_row = col >= 16;
     build_phase_factors<LOG2N>(fac, tid);
-    const int g = lane >> 5, col = lane & 31;
 
-    floatx16 acc[2];
+    floatx16 acc0, acc1;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[0][v] = acc[1][v] = 0.0f;
+    for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
 
-    const int nchunks = (L + kChunkL * kStages - 1) / (kChunkL * kStages) * kStages;
-    ContractStage st[kStages];
-    SplitOperands op[2];
+    const size_t xstride = (size_t)kBinBlock * ncol;  // complex floats between elements
+    // padding columns read the last transmit's spectrum (results discarded)
+    const float4* xp = reinterpret_cast<const float4*>(
+        X + spec_index(kb * kBinBlock + 2 * p, 0, min(ct * 32 + col, ntx - 1), L, ncol));
+    const float4* dp = phd + ((size_t)rt * 4 + p) * L * 16 + orow;
+
+    for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
+        const int cn = min(kAnchorChunk, L - c0);
+        __syncthreads();
+        build_anchors<LOG2N>(buf, fac, shift, kb, rt, M, L, c0, cn, tid);
+        __syncthreads();
+        const int half = (cn + 1) >> 1;
+        const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
+        const int e1 = __builtin_amdgcn_readfirstlane(min(c0 + cn, e0 + half));
+        const int last = e1 - 1;
+        auto load = [&](SplitLoads& q, int l0) {
 #pragma unroll
-    for (int u = 0; u < kStages; ++u) contract_load(st[u], X, shift, kb, ncol, ct, L, u * kChunkL, M, rt, tid);
-    __syncthreads();  // phase factors complete
-    split_store<LOG2N, F16>(st[0], xs[0], ws[0], fac, kb, 0, L, M, rt, tid, xscale);
-    contract_load(st[0], X, shift, kb, ncol, ct, L, kStages * kChunkL, M, rt, tid);
-    split_store<LOG2N, F16>(st[1], xs[1], ws[1], fac, kb, kChunkL, L, M, rt, tid, xscale);
-    contract_load(st[1], X, shift, kb, ncol, ct, L, (kStages + 1) * kChunkL, M, rt, tid);
-    __syncthreads();
-    split_read(op[0], xs[0], ws[0], col, g, wave);
-    __syncthreads();  // every wave has chunk 0's operands before buffer 0 takes chunk 2
-    for (int c0 = 0; c0 < nchunks; c0 += kStages) {
+            for (int e = 0; e < 4; ++e) {
+                const int l = min(l0 + 4 * g + e, last);
+                q.x[e] = xp[(size_t)l * (xstride / 2)];
+                q.d[e] = dp[(size_t)l * 16];
+                q.a[e] = buf[(l - c0) * 16 + orow];
+            }
+        };
+        if (e0 < e1) {
+            // whole groups of 8 elements, two groups of loads in flight; elements past the
+            // last one re-read it and enter with a zero phase
+            const int groups = (e1 - e0 + 7) / 8;
+            const int steps = (groups + 1) / 2;
+            SplitLoads q[2];
+            load(q[0], e0);
+            asm volatile("" ::: "memory");  // the prologue issues its loads in the loop's order
+            load(q[1], e0 + 8);
+            asm volatile("" ::: "memory");
+            int e = e0;
+            for (int it = 0; it < steps; ++it, e += 16) {
 #pragma unroll
-        for (int u = 0; u < kStages; ++u) {
-            const int c = c0 + u;
-            split_mfma<F16>(acc, op[u & 1]);
-            split_read(op[(u + 1) & 1], xs[(u + 1) & 1], ws[(u + 1) & 1], col, g, wave);
-            const int s2 = (u + 2) % kStages;
-            split_store<LOG2N, F16>(st[s2], xs[u & 1], ws[u & 1], fac, kb, (c + 2) * kChunkL, L, M, rt, tid, xscale);
-            contract_load(st[s2], X, shift, kb, ncol, ct, L, (c + 2 + kStages) * kChunkL, M, rt, tid);
-            __syncthreads();
+                for (int u = 0; u < 2; ++u) {
+                    const int l0 = e + 8 * u;
+                    const SplitLoads& c = q[u];
+                    uint32_t hv[8][4];  // per element: A hi/lo of both bins, B hi/lo of both bins
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const bool valid = l0 + 4 * g + k <= last;
+                        const float2 an = valid ? c.a[k] : make_float2(0.f, 0.f);
+                        const float2 w0 = cmul2(an, make_float2(c.d[k].x, c.d[k].y));
+                        const float2 w1 = cmul2(w0, make_float2(c.d[k].z, c.d[k].w));
+                        // A row pair: Re rows (Wr, -Wi), Im rows (Wi, Wr)
+                        split_pair<F16>(im_row ? w0.y : w0.x, im_row ? w0.x : -w0.y, hv[0][k], hv[1][k]);
+                        split_pair<F16>(im_row ? w1.y : w1.x, im_row ? w1.x : -w1.y, hv[2][k], hv[3][k]);
+                        const float4 x = c.x[k];
+                        split_pair<F16>(x.x * xscale, x.y * xscale, hv[4][k], hv[5][k]);
+                        split_pair<F16>(x.z * xscale, x.w * xscale, hv[6][k], hv[7][k]);
+                    }
+                    const u32x4 ah0 = {hv[0][0], hv[0][1], hv[0][2], hv[0][3]};
+                    const u32x4 al0 = {hv[1][0], hv[1][1], hv[1][2], hv[1][3]};
+                    const u32x4 ah1 = {hv[2][0], hv[2][1], hv[2][2], hv[2][3]};
+                    const u32x4 al1 = {hv[3][0], hv[3][1], hv[3][2], hv[3][3]};
+                    const u32x4 bh0 = {hv[4][0], hv[4][1], hv[4][2], hv[4][3]};
+                    const u32x4 bl0 = {hv[5][0], hv[5][1], hv[5][2], hv[5][3]};
+                    const u32x4 bh1 = {hv[6][0], hv[6][1], hv[6][2], hv[6][3]};
+                    const u32x4 bl1 = {hv[7][0], hv[7][1], hv[7][2], hv[7][3]};
+                    // this group's operands are in hv: the buffer takes the group two ahead
+                    load(q[u], l0 + 16);
+                    acc0 = mfma16<F16>(ah0, bl0, acc0);
+                    acc0 = mfma16<F16>(al0, bh0, acc0);
+                    acc0 = mfma16<F16>(ah0, bh0, acc0);
+                    acc1 = mfma16<F16>(ah1, bl1, acc1);
+                    acc1 = mfma16<F16>(al1, bh1, acc1);
+                    acc1 = mfma16<F16>(ah1, bh1, acc1);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
         }
     }
-    constexpr int kYCol = 16 * kBinBlock + 1;
-    static_assert(32 * kYCol * 8 <= (int)sizeof(xs), "result staging fits the spectrum buffers");
-    float2* yst = reinterpret_cast<float2*>(&xs[0][0]);
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(buf);
+    if (h == 1) {
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        yst[col * kYCol + ol * kBinBlock + wave] =
-            make_float2((acc[0][v] + acc[1][v]) * yscale, (acc[0][v + 8] + acc[1][v + 8]) * yscale);
+        for (int v = 0; v < 16; ++v) {
+            red[((p * 2 + 0) * 16 + v) * 64 + lane] = acc0[v];
+            red[((p * 2 + 1) * 16 + v) * 64 + lane] = acc1[v];
+        }
+    }
+    __syncthreads();
+    if (h == 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            acc0[v] += red[((p * 2 + 0) * 16 + v) * 64 + lane];
+            acc1[v] += red[((p * 2 + 1) * 16 + v) * 64 + lane];
+        }
+    }
+    __syncthreads();
+    float2* yst = buf;
+    if (h == 0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+            yst[col * kYCol + ol * kBinBlock + 2 * p] = make_float2(acc0[v] * yscale, acc0[v + 8] * yscale);
+            yst[col * kYCol + ol * kBinBlock + 2 * p + 1] = make_float2(acc1[v] * yscale, acc1[v + 8] * yscale);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -423,16 +431,17 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
 template <int LOG2N>
 __global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
                                                                      const int32_t* __restrict__ shift,
+                                                                     const float4* __restrict__ phd,
                                                                      float2* __restrict__ Y, int ntx, int M,
                                                                      int L, int ncol, int kpad) {
-    contract_body<LOG2N>(X, shift, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z);
+    contract_body<LOG2N>(X, shift, phd, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <int LOG2N, bool F16>
 __global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
-    const float2* __restrict__ X, const int32_t* __restrict__ shift, float2* __restrict__ Y, int ntx, int M, int L,
-    int ncol, int kpad, float xscale, float yscale) {
-    contract_split_body<LOG2N, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
+    const float2* __restrict__ X, const int32_t* __restrict__ shift, const float4* __restrict__ phd,
+    float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad, float xscale, float yscale) {
+    contract_split_body<LOG2N, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
                                     blockIdx.z);
 }
 
@@ -449,12 +458,13 @@ __global__ __launch_bounds__(kContractThreads) void contract_grouped(const Contr
     const int kb = local % e.nkb;
     local /= e.nkb;
     const int rt = local % e.nrt, ct = local / e.nrt;
+    const float4* phd = reinterpret_cast<const float4*>(ws + e.d_off);
     if constexpr (PREC == 0)
-        contract_body<LOG2N>(ws + e.x_off, plan + e.shift_off, ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt,
-                             ct);
+        contract_body<LOG2N>(ws + e.x_off, plan + e.shift_off, phd, ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad, kb,
+                             rt, ct);
     else
-        contract_split_body<LOG2N, PREC == 2>(ws + e.x_off, plan + e.shift_off, ws + e.y_off, e.ntx, e.M, e.L, e.ncol,
-                                              e.kpad, e.xscale, e.yscale, kb, rt, ct);
+        contract_split_body<LOG2N, PREC == 2>(ws + e.x_off, plan + e.shift_off, phd, ws + e.y_off, e.ntx, e.M, e.L,
+                                              e.ncol, e.kpad, e.xscale, e.yscale, kb, rt, ct);
 }
 
 template <int LOG2N>
@@ -471,47 +481,47 @@ hipError_t grouped_contract(int prec, const ContractEntry* tab, const int32_t* b
 }
 
 template <int LOG2N, bool F16>
-hipError_t contract_split(const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L, int ncol, int kpad,
-                          float xscale, hipStream_t st) {
+hipError_t contract_split(const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx, int M, int L,
+                          int ncol, int kpad, float xscale, hipStream_t st) {
     const dim3 grid((1 << LOG2N) / 2 / kBinBlock, (M + 15) / 16, ncol / 32);
-    hipLaunchKernelGGL((contract_split_kernel<LOG2N, F16>), grid, dim3(kContractThreads), 0, st, X, shift, Y, ntx, M,
-                       L, ncol, kpad, xscale, 1.0f / xscale);
+    hipLaunchKernelGGL((contract_split_kernel<LOG2N, F16>), grid, dim3(kContractThreads), 0, st, X, shift, phd, Y,
+                       ntx, M, L, ncol, kpad, xscale, 1.0f / xscale);
     return hipGetLastError();
 }
 
 template <int LOG2N>
-hipError_t contract(const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L, int ncol, int kpad,
-                    hipStream_t st) {
+hipError_t contract(const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx, int M, int L,
+                    int ncol, int kpad, hipStream_t st) {
     // bins 0 .. n/2 - 1; the Nyquist bin is summed by the inverse transform
     const dim3 grid((1 << LOG2N) / 2 / kBinBlock, (M + 15) / 16, ncol / 32);
-    hipLaunchKernelGGL((contract_kernel<LOG2N>), grid, dim3(kContractThreads), 0, st, X, shift, Y, ntx, M, L, ncol,
-                       kpad);
+    hipLaunchKernelGGL((contract_kernel<LOG2N>), grid, dim3(kContractThreads), 0, st, X, shift, phd, Y, ntx, M, L,
+                       ncol, kpad);
     return hipGetLastError();
 }
 
 template <bool F16>
-hipError_t launch_contract_split(int log2n, const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L,
-                                 int ncol, int kpad, float xscale, hipStream_t st) {
+hipError_t launch_contract_split(int log2n, const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx,
+                                 int M, int L, int ncol, int kpad, float xscale, hipStream_t st) {
     switch (log2n) {
-        case 8: return contract_split<8, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 9: return contract_split<9, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 10: return contract_split<10, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 11: return contract_split<11, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 12: return contract_split<12, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 13: return contract_split<13, F16>(X, shift, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 8: return contract_split<8, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 9: return contract_split<9, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 10: return contract_split<10, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 11: return contract_split<11, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 12: return contract_split<12, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
+        case 13: return contract_split<13, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_contract(int log2n, const float2* X, const int32_t* shift, float2* Y, int ntx, int M, int L,
-                           int ncol, int kpad, hipStream_t st) {
+hipError_t launch_contract(int log2n, const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx,
+                           int M, int L, int ncol, int kpad, hipStream_t st) {
     switch (log2n) {
-        case 8: return contract<8>(X, shift, Y, ntx, M, L, ncol, kpad, st);
-        case 9: return contract<9>(X, shift, Y, ntx, M, L, ncol, kpad, st);
-        case 10: return contract<10>(X, shift, Y, ntx, M, L, ncol, kpad, st);
-        case 11: return contract<11>(X, shift, Y, ntx, M, L, ncol, kpad, st);
-        case 12: return contract<12>(X, shift, Y, ntx, M, L, ncol, kpad, st);
-        case 13: return contract<13>(X, shift, Y, ntx, M, L, ncol, kpad, st);
+        case 8: return contract<8>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
+        case 9: return contract<9>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
+        case 10: return contract<10>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
+        case 11: return contract<11>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
+        case 12: return contract<12>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
+        case 13: return contract<13>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -555,9 +565,10 @@ namespace {
 
 struct DecomposeLayout {
     int log2n, K, kpad, ncol;
-    size_t x_off, y_off, total;
+    size_t x_off, d_off, y_off, total;
 };
 
+// workspace: spectra (contraction layout), phase steps, contracted spectra [N][M][kpad]
 bool decompose_layout(const kk_geom* g, int32_t N, int32_t M, int32_t tpad, DecomposeLayout* d) {
     const int lg = log2_exact(tpad);
     if (lg < kMinLog2Fft || lg > kMaxLog2Fft || g->T < 1 || g->T > tpad || g->L < 1 || N < 1 || M < 1) return false;
@@ -566,9 +577,26 @@ bool decompose_layout(const kk_geom* g, int32_t N, int32_t M, int32_t tpad, Deco
     d->kpad = (d->K + kBinBlock - 1) / kBinBlock * kBinBlock;
     d->ncol = (N + 31) / 32 * 32;
     d->x_off = 0;
-    d->y_off = d->x_off + align256((size_t)d->kpad * d->ncol * g->L * 8);
+    d->d_off = d->x_off + align256((size_t)d->kpad * d->ncol * g->L * 8);
+    d->y_off = d->d_off + align256(phase_step_floats4(M, g->L) * 16);
     d->total = d->y_off + align256((size_t)N * M * d->kpad * 8);
     return true;
+}
+
+// Forward transform (with the phase steps) and the per-bin contraction of one frame into Y.
+hipError_t decompose_front(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M,
+                           int32_t precision, const DecomposeLayout& d, unsigned char* w, float2* Y, hipStream_t st) {
+    float2* X = reinterpret_cast<float2*>(w + d.x_off);
+    float4* phd = reinterpret_cast<float4*>(w + d.d_off);
+    const PhaseSteps ph{shift_q, M, phd};
+    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st, &ph);
+    if (e != hipSuccess) return e;
+    if (precision == KK_PREC_FP32)
+        return launch_contract(d.log2n, X, shift_q, phd, Y, N, M, g->L, d.ncol, d.kpad, st);
+    if (precision == KK_PREC_BF16X3)
+        return launch_contract_split<false>(d.log2n, X, shift_q, phd, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
+    return launch_contract_split<true>(d.log2n, X, shift_q, phd, Y, N, M, g->L, d.ncol, d.kpad,
+                                       std::ldexp(1.0f, fp16_prescale_exponent(g->T)), st);
 }
 
 struct DasLayout {
@@ -616,21 +644,9 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
     if (ws_bytes < d.total) return KK_E_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     unsigned char* w = static_cast<unsigned char*>(ws);
-    float2* X = reinterpret_cast<float2*>(w + d.x_off);
     float2* Y = reinterpret_cast<float2*>(w + d.y_off);
-    if (launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st) != hipSuccess)
-        return KK_E_HIP;
-    hipError_t ce;
-    if (precision == KK_PREC_FP32) {
-        ce = launch_contract(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, st);
-    } else if (precision == KK_PREC_BF16X3) {
-        ce = launch_contract_split<false>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
-    } else {
-        const int e = fp16_prescale_exponent(g->T);
-        ce = launch_contract_split<true>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, std::ldexp(1.0f, e), st);
-    }
-    if (ce != hipSuccess) return KK_E_HIP;
-    NyquistSum nyq{X, shift_q, M, g->L, d.ncol};
+    if (decompose_front(rf, N, g, shift_q, M, precision, d, w, Y, st) != hipSuccess) return KK_E_HIP;
+    NyquistSum nyq{reinterpret_cast<const float2*>(w + d.x_off), shift_q, M, g->L, d.ncol};
     if (launch_fft_inverse(Y, N * M, d.kpad, d.log2n, reinterpret_cast<float2*>(rf_theta), g->T, st, &nyq) !=
         hipSuccess)
         return KK_E_HIP;
@@ -653,22 +669,11 @@ int32_t kk_decompose_spectrum(const int16_t* rf, int32_t N, const kk_geom* g, co
     DecomposeLayout d;
     if (!decompose_layout(g, N, M, tpad, &d)) return KK_E_ARG;
     if ((int64_t)N * g->L > 0x7fffffff || (int64_t)N * M > 0x7fffffff) return KK_E_ARG;
-    if (ws_bytes < d.y_off) return KK_E_WORKSPACE;  // the spectra only; Y is the caller's
+    if (ws_bytes < d.y_off) return KK_E_WORKSPACE;  // spectra and phase steps; Y is the caller's
     hipStream_t st = (hipStream_t)stream;
-    float2* X = static_cast<float2*>(ws);
     float2* Y = reinterpret_cast<float2*>(spec);
-    if (launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st) != hipSuccess)
+    if (decompose_front(rf, N, g, shift_q, M, precision, d, static_cast<unsigned char*>(ws), Y, st) != hipSuccess)
         return KK_E_HIP;
-    hipError_t ce;
-    if (precision == KK_PREC_FP32) {
-        ce = launch_contract(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, st);
-    } else if (precision == KK_PREC_BF16X3) {
-        ce = launch_contract_split<false>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
-    } else {
-        ce = launch_contract_split<true>(d.log2n, X, shift_q, Y, N, M, g->L, d.ncol, d.kpad,
-                                         std::ldexp(1.0f, fp16_prescale_exponent(g->T)), st);
-    }
-    if (ce != hipSuccess) return KK_E_HIP;
     const int from = tpad / 2;
     const int64_t n = (int64_t)N * M * (d.kpad - from);
     hipLaunchKernelGGL(zero_bins_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Y, (int64_t)N * M,

@@ -89,7 +89,7 @@ struct Words {
 struct FrameWork {
     kk_ensemble_frame_info info;
     int log2n, kpad, ncol, cls;
-    int64_t x_bytes, y_bytes, x_off_ws, y_off_ws;  // decomposition spectra within the group region
+    int64_t x_bytes, d_bytes, y_bytes, x_off_ws, d_off_ws, y_off_ws;  // decomposition buffers within the group region
     std::vector<int32_t> set_begin;                 // S + 1
     int ntiles;
 };
@@ -167,6 +167,7 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
         in.rf_theta_offset = ws / 8;
         ws = align_up(ws + (int64_t)fr.N * fr.M * g.T * 8, 256);
         w.x_bytes = align_up((int64_t)w.kpad * w.ncol * g.L * 8, 256);
+        w.d_bytes = align_up((int64_t)phase_step_floats4(fr.M, g.L) * 16, 256);
         w.y_bytes = align_up((int64_t)fr.N * fr.M * w.kpad * 8, 256);
     }
     for (int f = 0; f < nf; ++f) {
@@ -183,14 +184,15 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
     int ngroups = 0;
     for (int f = 0; f < nf; ++f) {
         FrameWork& w = fw[f];
-        const int64_t need = w.x_bytes + w.y_bytes;
+        const int64_t need = w.x_bytes + w.d_bytes + w.y_bytes;
         if (f == 0 || (budget > 0 && group_bytes + need > budget)) {
             ++ngroups;
             group_bytes = 0;
         }
         w.info.group = ngroups - 1;
         w.x_off_ws = ws_dec + group_bytes;
-        w.y_off_ws = w.x_off_ws + w.x_bytes;
+        w.d_off_ws = w.x_off_ws + w.x_bytes;
+        w.y_off_ws = w.d_off_ws + w.d_bytes;
         group_bytes += need;
         region = std::max(region, group_bytes);
     }
@@ -235,18 +237,23 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
                 FwdEntry a{};
                 a.rf_off = in.rf_offset;
                 a.x_off = w.x_off_ws / 8;
+                a.d_off = w.d_off_ws / 8;
+                a.shift_off = in.shift_offset;
+                a.M = in.M;
                 a.ntraces = in.N * in.L;
                 a.T = in.T;
                 a.L = in.L;
                 a.ncol = w.ncol;
                 a.kpad = w.kpad;
                 a.block0 = (int32_t)fb.size();
-                const int64_t nfb = (a.ntraces + 1) / 2;
+                // record pairs (transmits i, i+1 of one element), then the phase-step blocks
+                const int64_t nfb = (int64_t)in.L * ((in.N + 1) / 2) + phase_step_blocks(in.M, in.L, lg);
                 if (!check_blocks((int64_t)fb.size() + nfb)) return KK_E_ARG;
                 fb.insert(fb.end(), (size_t)nfb, e);
                 fe.push_back(a);
                 ContractEntry c{};
                 c.x_off = a.x_off;
+                c.d_off = a.d_off;
                 c.y_off = w.y_off_ws / 8;
                 c.shift_off = in.shift_offset;
                 c.ntx = in.N;
@@ -461,7 +468,7 @@ int32_t run_plan(const void* plan_host, const void* plan_dev, size_t plan_bytes,
             case LK_FWD:
                 if (stages & KK_STAGE_FFT)
                     e = launch_fft_forward_grouped(r.arg, reinterpret_cast<const FwdEntry*>(pd + r.tab_off),
-                                                   pd + r.aux_off, r.blocks, rf, wsf, st);
+                                                   pd + r.aux_off, r.blocks, rf, wsf, pd, st);
                 break;
             case LK_CONTRACT:
                 if (stages & KK_STAGE_CONTRACT)

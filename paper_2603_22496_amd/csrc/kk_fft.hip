@@ -4,15 +4,18 @@
 //
 // Stockham autosort in LDS with radix-16 passes (register-resident 16-point DFTs built from
 // radix-2/4 stages with exact internal constants) and one radix-2/4/8 pass for the remainder,
-// 256 threads per transform.  The first pass reads global memory directly (coalesced), every
-// later pass goes through one LDS round trip (the LDS array carries one pad slot per 16 points
-// so the strided writes of a radix-16 pass spread over the banks).  The twiddles of a butterfly,
-// W^(r k) for r = 1 .. R-1, come from one base twiddle W^k by a power tree (W^r = W^(r/2) W^(r -
-// r/2), at most four products deep); the base twiddle exp(-2 pi i m / n) is the product of two
-// factors, exp(-2 pi i (m >> (log2n-6)) / 64) and exp(-2 pi i (m mod n/64) / n), each evaluated in
-// FP64 by the workgroup into a small LDS table.
-// Forward transforms take two real int16 records per workgroup as the real and imaginary parts of one complex sequence and unpack them straight into the two masked
-// analytic spectra: for 0 < k < n/2, A[k] = Z[k] + conj(Z[n-k]) and
+// 256 threads per transform (512 at 8192 points).  Records enter LDS as 16-byte loads; every
+// pass goes through one LDS round trip (the LDS array carries one pad slot per 16 points so
+// the strided writes of a radix-16 pass spread over the banks).  A record at most half the
+// transform long has a zero upper half, which the first pass skips; an inverse transform whose
+// first half of outputs is kept computes only those in its last pass.  The twiddles of a
+// butterfly, W^(r k) for r = 1 .. R-1, come from one base twiddle W^k by a power tree (W^r =
+// W^(r/2) W^(r - r/2), at most four products deep); the base twiddle exp(-2 pi i m / n) is the
+// product of two factors, exp(-2 pi i (m >> (log2n-6)) / 64) and exp(-2 pi i (m mod n/64) / n),
+// each evaluated in FP64 by the workgroup into a small LDS table.
+// Forward transforms take two real int16 records per workgroup as the real and imaginary parts
+// of one complex sequence and unpack them straight into the two masked analytic spectra: for
+// 0 < k < n/2, A[k] = Z[k] + conj(Z[n-k]) and
 // B[k] = -i (Z[k] - conj(Z[n-k])) (the x2 of the analytic mask absorbs the 1/2 of the unpack);
 // A[0] = Re Z[0], B[0] = Im Z[0], likewise at k = n/2.
 #include <hip/hip_runtime.h>
@@ -23,7 +26,10 @@
 namespace kk {
 namespace {
 
-constexpr int kFftThreads = 256;
+// Threads per transform: 256, and 512 for the 8192-point transform, whose LDS footprint
+// (~70 KB) leaves room for only two transforms per CU (so each takes more waves).
+template <int LOG2N>
+constexpr int fft_threads() { return fft_threads_for(LOG2N); }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -185,19 +191,23 @@ __device__ __forceinline__ int out_index(int b, int r) {
     return (b / NS) * NS * R + k + r * NS;
 }
 
-// one Stockham pass LDS -> LDS (in place: all reads, barrier, all writes, barrier)
-template <int LOG2N, int R, int NS, bool INV>
+// one Stockham pass LDS -> LDS (in place: all reads, barrier, all writes, barrier).  HALF: the
+// first pass of a sequence whose upper half is zero (a record zero-padded to at least twice its
+// length): inputs r >= R/2 of every butterfly (n = b + r N/R >= N/2) are known zeros.
+template <int LOG2N, int R, int NS, bool INV, bool HALF = false>
 __device__ __forceinline__ void pass_lds(float2* data, const float2* fac, int tid) {
     constexpr int N = 1 << LOG2N;
     constexpr int NB = N / R;
-    constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+    constexpr int PER = (NB + fft_threads<LOG2N>() - 1) / fft_threads<LOG2N>();
+    static_assert(!HALF || NS == 1, "zero upper half only on the first pass");
     float2 v[PER][R];
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * kFftThreads;
+        const int b = tid + p * fft_threads<LOG2N>();
         if (b < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[p][r] = data[read_base<N, R>(b) + r * read_step<N, R>()];
+            for (int r = 0; r < R; ++r)
+                v[p][r] = (HALF && 2 * r >= R) ? make_float2(0.f, 0.f) : data[read_base<N, R>(b) + r * read_step<N, R>()];
             twiddle<LOG2N, R, NS, INV>(v[p], b, fac);
             Dft<R, INV>::run(v[p]);
         }
@@ -205,7 +215,7 @@ __device__ __forceinline__ void pass_lds(float2* data, const float2* fac, int ti
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-        const int b = tid + p * kFftThreads;
+        const int b = tid + p * fft_threads<LOG2N>();
         if (b < NB) {
 #pragma unroll
             for (int r = 0; r < R; ++r) data[write_base<N, R, NS>(b) + r * write_step<N, R, NS>()] = v[p][r];
@@ -214,34 +224,92 @@ __device__ __forceinline__ void pass_lds(float2* data, const float2* fac, int ti
     __syncthreads();
 }
 
-template <int LOG2N, int P, bool INV>
+template <int LOG2N, int P, bool INV, bool HALF = false>
 __device__ __forceinline__ void middle_passes(float2* data, const float2* fac, int tid) {
     using F = FftPlan<LOG2N>;
     if constexpr (P < F::NPASS - 1) {
-        pass_lds<LOG2N, F::radix(P), F::ns(P), INV>(data, fac, tid);
+        pass_lds<LOG2N, F::radix(P), F::ns(P), INV, HALF && P == 0>(data, fac, tid);
         middle_passes<LOG2N, P + 1, INV>(data, fac, tid);
     }
 }
 
+// The contraction's per-element phase steps (extra workgroups of a blocked forward launch):
+// thread e of phase block b handles entry (rt, l, o % 16) = e-th of nrt x L x 16 and writes
+// {D_2p, D_1} for p = 0..3.  Each D_j is evaluated from the exact integer turn count
+// (j shift) mod (n 2^22) in FP64 and rounded once to FP32.
+template <int LOG2N>
+__device__ __forceinline__ void phase_step_block(const int32_t* __restrict__ shift, int M, int L,
+                                                 float4* __restrict__ phd, int b) {
+    const int nrt = (M + 15) / 16;
+    const int64_t e = (int64_t)b * fft_threads<LOG2N>() + threadIdx.x;
+    if (e >= (int64_t)nrt * L * 16) return;
+    const int oo = (int)(e & 15);
+    const int64_t rl = e >> 4;
+    const int l = (int)(rl % L), rt = (int)(rl / L);
+    const int o = rt * 16 + oo;
+    float2 d[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) d[j] = make_float2(1.f, 0.f);
+    if (o < M) {
+        constexpr int64_t period = (int64_t)1 << (LOG2N + 22);
+        const int64_t s = shift[(size_t)o * L + l];
+#pragma unroll
+        for (int j = 1; j < 7; ++j) {
+            if (j != 1 && (j & 1)) continue;  // D_1, D_2, D_4, D_6
+            int64_t r = (j * s) % period;
+            if (r < 0) r += period;
+            double sn, cs;
+            sincospi(2.0 * (double)r / (double)period, &sn, &cs);
+            d[j] = make_float2((float)cs, (float)sn);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        phd[(((size_t)rt * 4 + p) * L + l) * 16 + oo] = make_float4(d[2 * p].x, d[2 * p].y, d[1].x, d[1].y);
+}
+
 // One record pair per workgroup: the two real records are the real and imaginary parts of one
-// complex FFT.  The records enter LDS as 16-byte loads (8 samples), zero-padded to n; the
-// spectra leave as one 64-byte run (8 bins) per thread and record.
-// Body of record pair blk of one frame (shared by the per-frame and the grouped launches).
+// complex FFT.  The records enter LDS as 16-byte loads (8 samples), zero-padded to n.
+// Blocked (contraction) layout: the pair is transmits i, i+1 of element l and the spectra
+// leave as whole 128-byte lines (8 bins of both records, four threads); trace layout:
+// records 2 blk, 2 blk + 1, and 64-byte runs (8 bins) of each record.
+// Body of block blk of one frame (shared by the per-frame and the grouped launches); blocked
+// launches carry the phase-step blocks after the record pairs.
 template <int LOG2N, bool BLOCKED>
 __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf, int ntraces, int T,
-                                                 float2* __restrict__ out, int L, int ncol, int kpad, int blk) {
+                                                 float2* __restrict__ out, int L, int ncol, int kpad, int blk,
+                                                 const int32_t* __restrict__ shift, int M, float4* __restrict__ phd) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
     __shared__ __attribute__((aligned(16))) float2 data[N + N / 16];
     __shared__ float2 fac[64 + N / 64];
     const int tid = threadIdx.x;
-    const int t0 = 2 * blk, t1 = t0 + 1;
-    const bool has1 = t1 < ntraces;
+    int t0, t1, i0 = 0, l0 = 0;
+    bool has1;
+    if constexpr (BLOCKED) {
+        const int ntx = ntraces / L;
+        const int npairs = (ntx + 1) / 2;
+        if (blk >= L * npairs) {  // uniform per workgroup, before any barrier
+            if (phd) phase_step_block<LOG2N>(shift, M, L, phd, blk - L * npairs);
+            return;
+        }
+        l0 = blk % L;
+        i0 = 2 * (blk / L);
+        t0 = i0 * L + l0;
+        t1 = t0 + L;
+        has1 = i0 + 1 < ntx;
+    } else {
+        t0 = 2 * blk;
+        t1 = t0 + 1;
+        has1 = t1 < ntraces;
+    }
     make_factors<LOG2N>(fac, tid);
     const int16_t* a = rf + (size_t)t0 * T;
     const int16_t* b = rf + (size_t)(has1 ? t1 : t0) * T;
+    // records at most half the transform long: the first pass never reads the upper half
+    const bool half = 2 * T <= N;
     if ((T & 7) == 0) {  // 8-sample groups: 16-byte aligned (records start at multiples of 16 B)
-        for (int g = tid; g < N / 8; g += kFftThreads) {
+        for (int g = tid; g < (half ? N / 16 : N / 8); g += fft_threads<LOG2N>()) {
             const int n0 = g * 8;
             int16_t xa[8], xb[8];
             if (n0 < T) {
@@ -256,19 +324,17 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
             for (int j = 0; j < 8; ++j) d[j] = make_float2((float)xa[j], has1 ? (float)xb[j] : 0.f);
         }
     } else {
-        for (int n = tid; n < N; n += kFftThreads)
+        for (int n = tid; n < N; n += fft_threads<LOG2N>())
             data[pad(n)] = make_float2(n < T ? (float)a[n] : 0.f, (n < T && has1) ? (float)b[n] : 0.f);
     }
     __syncthreads();
-    middle_passes<LOG2N, 0, false>(data, fac, tid);
+    if (half)
+        middle_passes<LOG2N, 0, false, true>(data, fac, tid);
+    else
+        middle_passes<LOG2N, 0, false>(data, fac, tid);
     pass_lds<LOG2N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, fac, tid);
-    // unpack the two real spectra with the analytic mask, two bins (16 bytes) per thread and
-    // record: four neighbouring threads complete one 64-byte run of 8 bins
-    const int i0 = t0 / L, l0 = t0 - i0 * L, i1 = t1 / L, l1 = t1 - i1 * L;
-    float2* o0 = BLOCKED ? out + ((size_t)i0 * L + l0) * kBinBlock : out + (size_t)t0 * kpad;
-    float2* o1 = BLOCKED ? out + ((size_t)i1 * L + l1) * kBinBlock : out + (size_t)t1 * kpad;
-    const unsigned kstride = BLOCKED ? (unsigned)(ncol * L * kBinBlock) : (unsigned)kBinBlock;  // between runs
-    for (int kp = tid; 2 * kp < kpad; kp += kFftThreads) {
+    // unpack the two real spectra with the analytic mask, two bins per thread and record
+    for (int kp = tid; 2 * kp < kpad; kp += fft_threads<LOG2N>()) {
         float2 A[2], B[2];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -286,9 +352,54 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
                 }
             }
         }
-        const unsigned off = (unsigned)(kp >> 2) * kstride + (unsigned)(2 * (kp & 3));
-        *reinterpret_cast<float4*>(o0 + off) = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
-        if (has1) *reinterpret_cast<float4*>(o1 + off) = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
+        if constexpr (BLOCKED) {
+            // bins 2kp, 2kp+1 of transmits i0 and i0+1 (zeros for a missing partner): the four
+            // threads of one bin block write one 128-byte line (64 bytes per record)
+            float4* o = reinterpret_cast<float4*>(out + spec_index(2 * kp, l0, i0, L, ncol));
+            o[0] = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
+            o[kBinBlock / 2] = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
+        } else {
+            // four neighbouring threads complete one 64-byte run of 8 bins per record
+            float2* o0 = out + (size_t)t0 * kpad;
+            float2* o1 = out + (size_t)t1 * kpad;
+            *reinterpret_cast<float4*>(o0 + 2 * kp) = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
+            if (has1) *reinterpret_cast<float4*>(o1 + 2 * kp) = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
+        }
+    }
+}
+
+// Last inverse pass straight to the output record, scaled by 1/N.  HALF: only the first N/2
+// samples are kept, i.e. outputs r < R/2 of every butterfly (n = k + r N/R).
+template <int LOG2N, bool HALF>
+__device__ __forceinline__ void inverse_last_pass(const float2* data, const float2* fac, float2* __restrict__ o,
+                                                  int T, int tid) {
+    using F = FftPlan<LOG2N>;
+    constexpr int N = F::N;
+    {
+        constexpr int P = F::NPASS - 1;
+        constexpr int R = F::radix(P);
+        constexpr int NS = F::ns(P);
+        constexpr int NB = N / R;
+        constexpr int PER = (NB + fft_threads<LOG2N>() - 1) / fft_threads<LOG2N>();
+        constexpr float scale = 1.0f / (float)N;
+        static_assert(NS * R == N, "last pass");
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int bb = tid + p * fft_threads<LOG2N>();
+            if (bb < NB) {
+                float2 v[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[r] = data[read_base<N, R>(bb) + r * read_step<N, R>()];
+                twiddle<LOG2N, R, NS, true>(v, bb, fac);
+                Dft<R, true>::run(v);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (HALF && 2 * r >= R) continue;
+                    const int n = out_index<N, R, NS>(bb, r);
+                    if (n < T) o[n] = make_float2(v[r].x * scale, v[r].y * scale);
+                }
+            }
+        }
     }
 }
 
@@ -309,17 +420,17 @@ __device__ __forceinline__ void fft_inverse_body(const float2* __restrict__ in, 
         // Eq. 3 at k = n/2: the advance s gives exp(i pi (s mod 2^23) / 2^22)
         const int i = t / nyq.M, o = t - (t / nyq.M) * nyq.M;
         float2 part = make_float2(0.f, 0.f);
-        for (int l = tid; l < nyq.L; l += kFftThreads) {
+        for (int l = tid; l < nyq.L; l += fft_threads<LOG2N>()) {
             const uint32_t s = (uint32_t)nyq.shift[(size_t)o * nyq.L + l];
             float sn, cs;
             sincospif((float)(s & 0x7FFFFFu) * (1.0f / 4194304.0f), &sn, &cs);
-            const float2 x = nyq.X[((((size_t)N / 16) * nyq.ncol + i) * nyq.L + l) * 8];
+            const float2 x = nyq.X[spec_index(N / 2, l, i, nyq.L, nyq.ncol)];
             part.x += cs * x.x - sn * x.y;
             part.y += cs * x.y + sn * x.x;
         }
         data[tid] = part;
         __syncthreads();
-        for (int h = kFftThreads / 2; h > 0; h >>= 1) {
+        for (int h = fft_threads<LOG2N>() / 2; h > 0; h >>= 1) {
             if (tid < h) data[tid] = cadd(data[tid], data[tid + h]);
             __syncthreads();
         }
@@ -329,16 +440,19 @@ __device__ __forceinline__ void fft_inverse_body(const float2* __restrict__ in, 
     {  // first pass from the K non-negative bins (negative bins are zero)
         constexpr int R = F::radix(0);
         constexpr int NB = N / R;
-        constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
+        constexpr int PER = (NB + fft_threads<LOG2N>() - 1) / fft_threads<LOG2N>();
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
-            const int bb = tid + p * kFftThreads;
+            const int bb = tid + p * fft_threads<LOG2N>();
             if (bb < NB) {
                 float2 v[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int k = bb + r * NB;
-                    v[r] = (NYQ && k == N / 2) ? ynyq : (k < K ? y[k] : make_float2(0.f, 0.f));
+                    if (2 * r > R)  // k > n/2: the negative bins are zero
+                        v[r] = make_float2(0.f, 0.f);
+                    else
+                        v[r] = (NYQ && k == N / 2) ? ynyq : (k < K ? y[k] : make_float2(0.f, 0.f));
                 }
                 Dft<R, true>::run(v);
 #pragma unroll
@@ -348,42 +462,23 @@ __device__ __forceinline__ void fft_inverse_body(const float2* __restrict__ in, 
         __syncthreads();
     }
     middle_passes<LOG2N, 1, true>(data, fac, tid);
-    {  // last pass straight to the output record, scaled by 1/N
-        constexpr int P = F::NPASS - 1;
-        constexpr int R = F::radix(P);
-        constexpr int NS = F::ns(P);
-        constexpr int NB = N / R;
-        constexpr int PER = (NB + kFftThreads - 1) / kFftThreads;
-        constexpr float scale = 1.0f / (float)N;
-        float2* o = out + (size_t)t * T;
-#pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            const int bb = tid + p * kFftThreads;
-            if (bb < NB) {
-                float2 v[R];
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[r] = data[read_base<N, R>(bb) + r * read_step<N, R>()];
-                twiddle<LOG2N, R, NS, true>(v, bb, fac);
-                Dft<R, true>::run(v);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int n = out_index<N, R, NS>(bb, r);
-                    if (n < T) o[n] = make_float2(v[r].x * scale, v[r].y * scale);
-                }
-            }
-        }
-    }
+    if (2 * T <= N)
+        inverse_last_pass<LOG2N, true>(data, fac, out + (size_t)t * T, T, tid);
+    else
+        inverse_last_pass<LOG2N, false>(data, fac, out + (size_t)t * T, T, tid);
 }
 
+
 template <int LOG2N, bool BLOCKED>
-__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
+__global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
                                                                   int T, float2* __restrict__ out, int L, int ncol,
-                                                                  int kpad) {
-    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x);
+                                                                  int kpad, const int32_t* __restrict__ shift, int M,
+                                                                  float4* __restrict__ phd) {
+    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x, shift, M, phd);
 }
 
 template <int LOG2N, bool NYQ>
-__global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* __restrict__ in, int kpad,
+__global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_inverse_kernel(const float2* __restrict__ in, int kpad,
                                                                   float2* __restrict__ out, int T,
                                                                   NyquistSum nyq) {
     fft_inverse_body<LOG2N, NYQ>(in, kpad, out, T, nyq, blockIdx.x);
@@ -392,17 +487,19 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(const float2* 
 // Grouped launches over the frames of one FFT-length class: block b runs record pair (or
 // record) b - block0 of frame entry blk[b].
 template <int LOG2N>
-__global__ __launch_bounds__(kFftThreads) void fft_forward_grouped(const FwdEntry* __restrict__ tab,
+__global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_forward_grouped(const FwdEntry* __restrict__ tab,
                                                                    const int32_t* __restrict__ blk,
                                                                    const int16_t* __restrict__ rf,
-                                                                   float2* __restrict__ ws) {
+                                                                   float2* __restrict__ ws,
+                                                                   const int32_t* __restrict__ plan) {
     const FwdEntry e = tab[blk[blockIdx.x]];
     fft_forward_body<LOG2N, true>(rf + e.rf_off, e.ntraces, e.T, ws + e.x_off, e.L, e.ncol, e.kpad,
-                                  (int)blockIdx.x - e.block0);
+                                  (int)blockIdx.x - e.block0, plan + e.shift_off, e.M,
+                                  reinterpret_cast<float4*>(ws + e.d_off));
 }
 
 template <int LOG2N>
-__global__ __launch_bounds__(kFftThreads) void fft_inverse_grouped(const InvEntry* __restrict__ tab,
+__global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_inverse_grouped(const InvEntry* __restrict__ tab,
                                                                    const int32_t* __restrict__ blk,
                                                                    float2* __restrict__ ws,
                                                                    const int32_t* __restrict__ plan) {
@@ -413,24 +510,28 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_grouped(const InvEntr
 
 template <int LOG2N>
 hipError_t fwd(const int16_t* rf, int ntraces, int T, float2* out, bool blocked, int L, int ncol, int kpad,
-               hipStream_t st) {
-    const int blocks = (ntraces + 1) / 2;  // one record pair per workgroup
-    if (blocked)
-        hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces, T,
-                           out, L, ncol, kpad);
-    else
-        hipLaunchKernelGGL((fft_forward_kernel<LOG2N, false>), dim3(blocks), dim3(kFftThreads), 0, st, rf, ntraces,
-                           T, out, L, ncol, kpad);
+               hipStream_t st, const PhaseSteps* ph) {
+    if (blocked) {
+        // one record pair (transmits i, i+1 of one element) per workgroup, then the phase steps
+        const int64_t pairs = (int64_t)L * ((ntraces / L + 1) / 2);
+        const int64_t pblocks = ph ? phase_step_blocks(ph->M, L, LOG2N) : 0;
+        hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3((unsigned)(pairs + pblocks)), dim3(fft_threads<LOG2N>()), 0,
+                           st, rf, ntraces, T, out, L, ncol, kpad, ph ? ph->shift : nullptr, ph ? ph->M : 0,
+                           ph ? ph->phd : nullptr);
+    } else {
+        hipLaunchKernelGGL((fft_forward_kernel<LOG2N, false>), dim3((ntraces + 1) / 2), dim3(fft_threads<LOG2N>()), 0, st, rf,
+                           ntraces, T, out, L, ncol, kpad, nullptr, 0, nullptr);
+    }
     return hipGetLastError();
 }
 
 template <int LOG2N>
 hipError_t inv(const float2* in, int ntraces, int kpad, float2* out, int T, hipStream_t st, const NyquistSum* nyq) {
     if (nyq)
-        hipLaunchKernelGGL((fft_inverse_kernel<LOG2N, true>), dim3(ntraces), dim3(kFftThreads), 0, st, in, kpad, out,
+        hipLaunchKernelGGL((fft_inverse_kernel<LOG2N, true>), dim3(ntraces), dim3(fft_threads<LOG2N>()), 0, st, in, kpad, out,
                            T, *nyq);
     else
-        hipLaunchKernelGGL((fft_inverse_kernel<LOG2N, false>), dim3(ntraces), dim3(kFftThreads), 0, st, in, kpad,
+        hipLaunchKernelGGL((fft_inverse_kernel<LOG2N, false>), dim3(ntraces), dim3(fft_threads<LOG2N>()), 0, st, in, kpad,
                            out, T, NyquistSum{nullptr, nullptr, 1, 1, 32});
     return hipGetLastError();
 }
@@ -438,28 +539,28 @@ hipError_t inv(const float2* in, int ntraces, int kpad, float2* out, int T, hipS
 }  // namespace
 
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
-                              int ncol, int kpad, hipStream_t st) {
+                              int ncol, int kpad, hipStream_t st, const PhaseSteps* ph) {
     switch (log2n) {
-        case 8: return fwd<8>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
-        case 9: return fwd<9>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
-        case 10: return fwd<10>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
-        case 11: return fwd<11>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
-        case 12: return fwd<12>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
-        case 13: return fwd<13>(rf, ntraces, T, out, blocked, L, ncol, kpad, st);
+        case 8: return fwd<8>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
+        case 9: return fwd<9>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
+        case 10: return fwd<10>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
+        case 11: return fwd<11>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
+        case 12: return fwd<12>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
+        case 13: return fwd<13>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_fft_forward_grouped(int log2n, const FwdEntry* tab, const int32_t* blk, int blocks,
-                                      const int16_t* rf, float2* ws, hipStream_t st) {
-    const dim3 g(blocks), b(kFftThreads);
+                                      const int16_t* rf, float2* ws, const int32_t* plan, hipStream_t st) {
+    const dim3 g(blocks);
     switch (log2n) {
-        case 8: hipLaunchKernelGGL(fft_forward_grouped<8>, g, b, 0, st, tab, blk, rf, ws); break;
-        case 9: hipLaunchKernelGGL(fft_forward_grouped<9>, g, b, 0, st, tab, blk, rf, ws); break;
-        case 10: hipLaunchKernelGGL(fft_forward_grouped<10>, g, b, 0, st, tab, blk, rf, ws); break;
-        case 11: hipLaunchKernelGGL(fft_forward_grouped<11>, g, b, 0, st, tab, blk, rf, ws); break;
-        case 12: hipLaunchKernelGGL(fft_forward_grouped<12>, g, b, 0, st, tab, blk, rf, ws); break;
-        case 13: hipLaunchKernelGGL(fft_forward_grouped<13>, g, b, 0, st, tab, blk, rf, ws); break;
+        case 8: hipLaunchKernelGGL(fft_forward_grouped<8>, g, dim3(fft_threads<8>()), 0, st, tab, blk, rf, ws, plan); break;
+        case 9: hipLaunchKernelGGL(fft_forward_grouped<9>, g, dim3(fft_threads<9>()), 0, st, tab, blk, rf, ws, plan); break;
+        case 10: hipLaunchKernelGGL(fft_forward_grouped<10>, g, dim3(fft_threads<10>()), 0, st, tab, blk, rf, ws, plan); break;
+        case 11: hipLaunchKernelGGL(fft_forward_grouped<11>, g, dim3(fft_threads<11>()), 0, st, tab, blk, rf, ws, plan); break;
+        case 12: hipLaunchKernelGGL(fft_forward_grouped<12>, g, dim3(fft_threads<12>()), 0, st, tab, blk, rf, ws, plan); break;
+        case 13: hipLaunchKernelGGL(fft_forward_grouped<13>, g, dim3(fft_threads<13>()), 0, st, tab, blk, rf, ws, plan); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -467,14 +568,14 @@ hipError_t launch_fft_forward_grouped(int log2n, const FwdEntry* tab, const int3
 
 hipError_t launch_fft_inverse_grouped(int log2n, const InvEntry* tab, const int32_t* blk, int blocks, float2* ws,
                                       const int32_t* plan, hipStream_t st) {
-    const dim3 g(blocks), b(kFftThreads);
+    const dim3 g(blocks);
     switch (log2n) {
-        case 8: hipLaunchKernelGGL(fft_inverse_grouped<8>, g, b, 0, st, tab, blk, ws, plan); break;
-        case 9: hipLaunchKernelGGL(fft_inverse_grouped<9>, g, b, 0, st, tab, blk, ws, plan); break;
-        case 10: hipLaunchKernelGGL(fft_inverse_grouped<10>, g, b, 0, st, tab, blk, ws, plan); break;
-        case 11: hipLaunchKernelGGL(fft_inverse_grouped<11>, g, b, 0, st, tab, blk, ws, plan); break;
-        case 12: hipLaunchKernelGGL(fft_inverse_grouped<12>, g, b, 0, st, tab, blk, ws, plan); break;
-        case 13: hipLaunchKernelGGL(fft_inverse_grouped<13>, g, b, 0, st, tab, blk, ws, plan); break;
+        case 8: hipLaunchKernelGGL(fft_inverse_grouped<8>, g, dim3(fft_threads<8>()), 0, st, tab, blk, ws, plan); break;
+        case 9: hipLaunchKernelGGL(fft_inverse_grouped<9>, g, dim3(fft_threads<9>()), 0, st, tab, blk, ws, plan); break;
+        case 10: hipLaunchKernelGGL(fft_inverse_grouped<10>, g, dim3(fft_threads<10>()), 0, st, tab, blk, ws, plan); break;
+        case 11: hipLaunchKernelGGL(fft_inverse_grouped<11>, g, dim3(fft_threads<11>()), 0, st, tab, blk, ws, plan); break;
+        case 12: hipLaunchKernelGGL(fft_inverse_grouped<12>, g, dim3(fft_threads<12>()), 0, st, tab, blk, ws, plan); break;
+        case 13: hipLaunchKernelGGL(fft_inverse_grouped<13>, g, dim3(fft_threads<13>()), 0, st, tab, blk, ws, plan); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -5,9 +5,38 @@
 
 namespace kk {
 
-// Bins per block of the spectrum layout used by the contraction: the analytic spectrum of
-// trace (i, l) is stored as X[k / 8][i][l][k % 8] so that one 64-byte run holds 8 bins.
+// Bins per block of the spectrum layout used by the contraction (one contraction workgroup
+// per block).  Bin k of the analytic spectrum of record (i, l) sits at
+//   X[(((k / 8) L + l) ncol + i) 8 + k % 8]
+// (complex float units, ncol = transmits padded to a multiple of 32): per block and element,
+// one 64-byte run of 8 bins per transmit column.  The forward FFT transforms transmits i and
+// i+1 of one element together, so its four threads of one block write one whole 128-byte
+// line; a contraction wave reads 16 bytes of every run of one block and element (the four
+// waves of its workgroup read the rest of the same lines).
 constexpr int kBinBlock = 8;
+
+__host__ __device__ inline size_t spec_index(int k, int l, int i, int L, int ncol) {
+    return (((size_t)(k >> 3) * L + l) * ncol + i) * 8 + (k & 7);
+}
+
+// Per-element phase steps of the contraction, D_j[o][l] = exp(2 pi i ((j shift[o][l]) mod (n 2^22))
+// / (n 2^22)) (n the FFT length): float4 {D_2p, D_1} at PhD[((rt 4 + p) L + l) 16 + o % 16],
+// rt = o / 16, p = 0..3; rows o >= M hold D = 1.  Written by the forward FFT launch.
+inline size_t phase_step_floats4(int M, int L) { return (size_t)((M + 15) / 16) * 4 * (size_t)L * 16; }
+
+// Threads per workgroup of the FFT kernels for a transform of 2^log2n points.
+constexpr int fft_threads_for(int log2n) { return log2n >= 13 ? 512 : 256; }
+// Workgroups of a blocked forward launch that write the phase steps (after the record pairs).
+inline int64_t phase_step_blocks(int M, int L, int log2n) {
+    const int64_t t = fft_threads_for(log2n);
+    return ((int64_t)phase_step_floats4(M, L) / 4 + t - 1) / t;
+}
+
+struct PhaseSteps {
+    const int32_t* shift;  // [M][L] Q.22 advances
+    int M;
+    float4* phd;           // out, phase_step_floats4(M, L) entries
+};
 
 constexpr int kMinLog2Fft = 8;
 constexpr int kMaxLog2Fft = 13;
@@ -21,15 +50,18 @@ inline int log2_exact(int64_t n) {
 
 // Analytic spectra of ntraces real int16 records of T samples, zero-padded to 2^log2n
 // (mask: DC x1, 1..n/2-1 x2, n/2 x1).  Traces are transformed two per workgroup as the real
-// and imaginary parts of one complex FFT.  Output bins k = 0..n/2:
-//   blocked: out[((k / 8) * ncol + t / L) * L + t % L][k % 8]   (contraction layout)
+// and imaginary parts of one complex FFT.  Output bins k = 0..kpad-1 (zero above n/2):
+//   blocked: out[spec_index(k, l, i, L, ncol)] for record t = i L + l (contraction layout;
+//            records i and i+1 of element l share a workgroup, a missing partner record of
+//            an odd transmit count is written as zeros); the launch also writes the phase
+//            steps *ph of the contraction (extra workgroups), when ph is given
 //   else:    out[t * kpad + k]                                   (trace layout)
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
-                              int ncol, int kpad, hipStream_t st);
+                              int ncol, int kpad, hipStream_t st, const PhaseSteps* ph = nullptr);
 
 // Where the Nyquist bin of record t = i * M + o is not stored but summed by the inverse
 // transform itself: Y[n/2] = sum_l exp(i pi shift[o][l] / 2^22) X[i][l][n/2] (Eq. 3 at k = n/2),
-// X in the bin-blocked layout.
+// X in the contraction layout (spec_index).
 struct NyquistSum {
     const float2* X;
     const int32_t* shift;
@@ -60,11 +92,14 @@ int fp16_prescale_exponent(int T);
 // the packed intensities (float) or the ensemble plan (int32 words).
 struct FwdEntry {
     int64_t rf_off;          // channel data of the frame, [N][L][T]
-    int64_t x_off;           // workspace: bin-blocked analytic spectra
+    int64_t x_off;           // workspace: analytic spectra in the contraction layout
+    int64_t d_off;           // workspace: phase steps of the contraction (float2 units)
     int32_t ntraces, T, L, ncol, kpad, block0;
+    int32_t shift_off, M;    // plan: shift table [M][L]
 };
 struct ContractEntry {
     int64_t x_off, y_off;    // workspace: spectra in, contracted spectra [N][M][kpad] out
+    int64_t d_off;           // workspace: phase steps (float2 units)
     int32_t shift_off;       // plan: shift table [M][L]
     int32_t ntx, M, L, ncol, kpad, nkb, nrt, block0;
     float xscale, yscale;    // split-precision prescale and its inverse
@@ -86,14 +121,14 @@ struct ReduceEntry {
     int64_t inten_off;       // intensities [X][Z], or -1
     int32_t K, S, npix, mode, block0, pad;
 };
-static_assert(sizeof(FwdEntry) == 40 && sizeof(ContractEntry) == 64 && sizeof(InvEntry) == 56 &&
+static_assert(sizeof(FwdEntry) == 56 && sizeof(ContractEntry) == 72 && sizeof(InvEntry) == 56 &&
                   sizeof(GatherEntry) == 40 && sizeof(ReduceEntry) == 48,
               "work table layout");
 
 constexpr int kQueueLists = 8;  // gather work lists, one per XCD
 
 hipError_t launch_fft_forward_grouped(int log2n, const FwdEntry* tab, const int32_t* blk, int blocks,
-                                      const int16_t* rf, float2* ws, hipStream_t st);
+                                      const int16_t* rf, float2* ws, const int32_t* plan, hipStream_t st);
 hipError_t launch_contract_grouped(int log2n, int precision, const ContractEntry* tab, const int32_t* blk,
                                    int blocks, float2* ws, const int32_t* plan, hipStream_t st);
 hipError_t launch_fft_inverse_grouped(int log2n, const InvEntry* tab, const int32_t* blk, int blocks, float2* ws,
