@@ -513,6 +513,23 @@ int32_t kk_net_merge(const float* out, const float* scale, const int32_t* bins, 
  * kernel (so that it may be captured into a graph).  Errors: KK_E_NULL, KK_E_ARG, KK_E_HIP. */
 int32_t kk_clear(void* dev, size_t bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * kk_beamform_static (device) - kk_beamform without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and errors as kk_beamform minus ws: the
+ * partial images of a split plan sit in a fixed device array inside the library, one copy per
+ * GPU of kk_beamform_static_max_bytes() bytes (16 MiB), held until the process ends.
+ * The call allocates nothing.  Errors: as kk_beamform; KK_E_WORKSPACE also when the plan needs
+ * more than kk_beamform_static_max_bytes() (kk_beamform_workspace_bytes(plan) tells), KK_E_HIP
+ * when the array's address cannot be obtained.  Every call on one GPU uses that GPU's array:
+ * calls that overlap in time on one GPU (several streams or threads) race and must not be
+ * issued; calls in one stream are ordered and safe.
+ * ------------------------------------------------------------------------------------- */
+size_t kk_beamform_static_max_bytes(void);
+int32_t kk_beamform_static(const float* rf_theta, int32_t N, int32_t M, int32_t T,
+                           const void* plan_host, const void* plan_dev, size_t plan_bytes,
+                           float* image, float* intensity, int32_t mode, void* stream);
+
 /* Human-readable name of a kk_status value (static string, never NULL). */
 const char* kk_status_string(int32_t status);
 

@@ -20,7 +20,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkk.so")
 
-HIP_SOURCES = ["kk_beamform.hip", "kk_fft.hip", "kk_decompose.hip", "kk_ensemble.hip", "kk_complete.hip"]
+HIP_SOURCES = ["kk_beamform.hip", "kk_fft.hip", "kk_decompose.hip", "kk_ensemble.hip", "kk_complete.hip",
+               "kk_static.hip"]
 HOST_SOURCES = ["kk_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -40,7 +40,7 @@ EXPORTS = [
     "kk_spectrum_bins", "kk_decompose_spectrum", "kk_spectrum_inverse",
     "kk_net_param_count", "kk_net_state_bytes", "kk_net_workspace_bytes", "kk_net_load", "kk_net_read",
     "kk_net_prepare", "kk_net_forward", "kk_net_backward", "kk_net_adam", "kk_net_train_step", "kk_net_merge",
-    "kk_clear",
+    "kk_clear", "kk_beamform_static", "kk_beamform_static_max_bytes",
 ]
 NET_LAYERS, NET_WIDTH, NET_IN = 6, 32, 8
 NET_PARAMS, NET_GRADS, NET_MOMENT1, NET_MOMENT2 = 0, 1, 2, 3
@@ -145,6 +145,7 @@ def lib():
                                   _vp, _vp, _sz, _vp],
             "kk_net_merge": [_vp, _vp, _vp, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp],
             "kk_clear": [_vp, _sz, _vp],
+            "kk_beamform_static": [_vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp, _vp, _i32, _vp],
             "kk_ensemble_autotune": [ctypes.POINTER(EnsembleFrame), _i32, _i32, ctypes.c_int64, _vp, _sz, _vp, _vp,
                                      _vp, _vp, _sz, _i32, _vp, ctypes.POINTER(EnsembleTuning),
                                      ctypes.POINTER(ctypes.c_float)],
@@ -160,6 +161,8 @@ def lib():
         L.das_workspace_bytes.restype = _sz
         L.kk_beamform_workspace_bytes.argtypes = [_vp, _sz]
         L.kk_beamform_workspace_bytes.restype = _sz
+        L.kk_beamform_static_max_bytes.argtypes = []
+        L.kk_beamform_static_max_bytes.restype = _sz
         for name in ("kk_net_param_count", "kk_net_state_bytes"):
             getattr(L, name).argtypes = []
             getattr(L, name).restype = _sz
@@ -349,6 +352,21 @@ def beamform(rf_theta, plan_host: np.ndarray, plan_dev, image=None, intensity=No
                            ws.numel() * ws.element_size() if ws is not None else 0, _stream(stream))
     _bind(stream, *new)
     _check("kk_beamform", st)
+    return image
+
+
+def beamform_static_max_bytes() -> int:
+    return int(lib().kk_beamform_static_max_bytes())
+
+
+def beamform_static(rf_theta, plan_host: np.ndarray, plan_dev, image, intensity=None,
+                    mode: int = COMPOUND_COHERENT, stream=None):
+    """kk_beamform without a workspace (see kk_beamform_static): the caller passes the outputs."""
+    N, M, T = rf_theta.shape
+    st = lib().kk_beamform_static(_dev(rf_theta), N, M, T, plan_host.ctypes.data_as(_vp), _dev(plan_dev),
+                                  plan_host.nbytes, _dev(image), _dev(intensity) if intensity is not None else None,
+                                  mode, _stream(stream))
+    _check("kk_beamform_static", st)
     return image
 
 
