@@ -1,18 +1,16 @@
 // Eq. 3 receive plane-wave decomposition on gfx950, evaluated in the temporal-frequency
 // domain (Sec. II-F):
 //   1. analytic spectra of the N*L zero-padded records (kk_fft.hip, two records per FFT),
-//      stored bin-blocked X[k/8][i][l][k%8];
+//      stored bin-blocked (spec_index: 64-byte runs of 8 bins per element and transmit); the
+//      same launch writes the phase tables of step 2 (PhaseTables);
 //   2. per bin k the complex contraction Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] with
 //      W_k[o][l] = exp(2 pi i r / (n 2^22)), r = (k shift[o][l]) mod (n 2^22), on MFMA
 //      (v_mfma_f32_32x32x2_f32: one complex element l per instruction, 16 receive angles x
-//      {Re, Im} rows by 32 transmit columns; 8 bins per workgroup, one per wave, the spectrum
-//      staged through LDS 16 elements at a time in a software pipeline across chunks);
+//      {Re, Im} rows by 32 transmit columns; 8 bins per workgroup, a bin pair per wave);
 //   3. inverse FFT of each (i, o) spectrum, first T samples.
-// The phase is formed exactly in integers; only the reduced fraction becomes floating point:
-// W = E[r >> 22] * exp(2 pi i (r mod 2^22) / (n 2^22)), with E[m] = exp(2 pi i m / n) the
-// product of two FP64-evaluated factor tables and the small second factor (|angle| < 2 pi / n)
-// by its Taylor series.  Within a bin block only the first bin's phase and the one-bin step are
-// evaluated so; the other bins are products of the step's powers (a few roundings deep).
+// Every phase comes from an exact integer turn count evaluated in FP64 and rounded once: the
+// anchor W_{8 kb} of each bin block and the steps D_j (j = 0..7) within a block, so that
+// W_{8 kb + j} = W_{8 kb} D_j is one complex product (two roundings) away from exact.
 // Also the DAS comparator entry point (analytic channel data + delay-gather).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -33,168 +31,164 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // elements, and the two halves are summed at the end.
 constexpr int kContractWaves = 8;
 constexpr int kContractThreads = kContractWaves * 64;
-// Elements whose anchor phases W_{8 kb}[o][l] sit in LDS at once.
+// Elements whose anchors sit in LDS at once.
 constexpr int kAnchorChunk = 256;
 // Elements whose operand loads are in flight per wave.
 constexpr int kDepth = 8;
+// Anchor rows in LDS: each half of a chunk is followed by 2 kDepth zero rows, which the
+// software pipeline reads past the half's last element (those elements enter with zero phase).
+constexpr int kAnchorRows = kAnchorChunk + 4 * kDepth;
 // Result staging per transmit column: 16 angles x 8 bins and a pad (a half-wave's 32 columns
 // then write 64 distinct banks).
 constexpr int kYCol = 16 * kBinBlock + 1;
-constexpr int kBufFloat2 = 32 * kYCol;  // >= anchors (kAnchorChunk x 16) and the half sums (4096)
-static_assert(kBufFloat2 >= kAnchorChunk * 16 && kBufFloat2 >= 4096, "LDS buffer");
-
-// exp(+2 pi i ((k s) mod (n 2^22)) / (n 2^22)) for 0 <= k < 2^23, any int32 s: the turn count
-// is reduced exactly with 24-bit products (k s = k s_hi 2^22 + k s_lo, s_lo < 2^22), the coarse
-// part m / n is the product of the two factor tables and the remaining fraction (< 1/n turn)
-// comes from its Taylor series.
-template <int LOG2N>
-__device__ __forceinline__ float2 shear_phase(uint32_t k, int32_t s, const float2* fac) {
-    constexpr float kFine = 6.283185307179586f / (float)(1 << LOG2N) / 4194304.0f;
-    const uint32_t s_lo = (uint32_t)s & 0x3FFFFFu;
-    const int32_t s_hi = s >> 22;
-    const uint64_t p = (uint64_t)(k & 0xFFFFFFu) * (uint64_t)s_lo;         // 24 x 22-bit product
-    const uint32_t plo = (uint32_t)p;
-    const uint32_t coarse = ((uint32_t)(p >> 22) + (uint32_t)__mul24((int)k, s_hi)) & ((1u << LOG2N) - 1);
-    const float ph = (float)(plo & 0x3FFFFFu) * kFine;
-    const float p2 = ph * ph;
-    const float cf = __builtin_fmaf(p2, __builtin_fmaf(p2, 1.0f / 24.0f, -0.5f), 1.0f);
-    const float sf = ph * __builtin_fmaf(p2, -1.0f / 6.0f, 1.0f);
-    const float2 a = fac[coarse >> (LOG2N - 6)], b = fac[64 + (coarse & ((1u << (LOG2N - 6)) - 1))];
-    const float2 e = make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-    return make_float2(e.x * cf - e.y * sf, e.x * sf + e.y * cf);
-}
+constexpr int kBufFloat2 = kAnchorRows * 16 > 32 * kYCol ? kAnchorRows * 16 : 32 * kYCol;
+static_assert(kBufFloat2 >= 4096, "LDS buffer holds the half sums");
+// Anchor loads per thread of one chunk (16-byte pieces, 8 per element).
+constexpr int kAnchorLoads = (kAnchorChunk * 8 + kContractThreads - 1) / kContractThreads;
 
 __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// exp(+2 pi i m / n) = exp(2 pi i (m >> (log2n - 6)) / 64) exp(2 pi i (m mod n/64) / n): the
-// two factor tables, evaluated in FP64
-template <int LOG2N>
-__device__ __forceinline__ void build_phase_factors(float2* fac, int tid) {
-    constexpr int N = 1 << LOG2N;
-    if (tid < 64 + N / 64) {
-        double sn, cs;
-        sincospi(tid < 64 ? 2.0 * tid / 64.0 : 2.0 * (tid - 64) / (double)N, &sn, &cs);
-        fac[tid] = make_float2((float)cs, (float)sn);
+// Raw buffer view of nbytes at p (gfx9 descriptor: 32-bit data format, no swizzle): loads take
+// a per-lane and a wave-uniform byte offset with no vector address arithmetic, and loads past
+// nbytes return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void* p, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buffer_load2(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane_off, (int)off, 0));
+}
+__device__ __forceinline__ float4 buffer_load4(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)lane_off, (int)off, 0));
+}
+
+// Anchors of elements [c0, c0 + cn) of one bin block and receive tile: global -> registers
+// (issued first, so that the caller's operand loads overlap them; indexes past the chunk
+// re-read its last piece) ...
+__device__ __forceinline__ void anchor_load(float4 (&v)[kAnchorLoads], const float2* __restrict__ anc, int c0, int cn,
+                                            int tid) {
+    const float4* src = reinterpret_cast<const float4*>(anc) + (size_t)c0 * 8;
+#pragma unroll
+    for (int u = 0; u < kAnchorLoads; ++u) v[u] = src[min(tid + u * kContractThreads, cn * 8 - 1)];
+}
+// ... -> LDS rows: element c0 + r at row r + (r >= split ? gap : 0); the gap rows after each
+// part are zero.
+__device__ __forceinline__ void anchor_store(const float4 (&v)[kAnchorLoads], float2* buf, int cn, int split, int gap,
+                                             int tid) {
+    float4* dst = reinterpret_cast<float4*>(buf);
+#pragma unroll
+    for (int u = 0; u < kAnchorLoads; ++u) {
+        const int f = tid + u * kContractThreads;
+        if (f < cn * 8) dst[f + (f >= split * 8 ? gap * 8 : 0)] = v[u];
+    }
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int f = tid; f < gap * 8; f += kContractThreads) {
+        dst[split * 8 + f] = z;
+        dst[(cn + gap) * 8 + f] = z;
     }
 }
 
-// Anchor phases of elements [c0, c0 + cn) of one bin block and receive tile:
-// anc[(l - c0) 16 + o % 16] = W_{8 kb}[o][l] (zero for o >= M), evaluated exactly.
-template <int LOG2N>
-__device__ __forceinline__ void build_anchors(float2* anc, const float2* fac, const int32_t* __restrict__ shift,
-                                              int kb, int rt, int M, int L, int c0, int cn, int tid) {
-    for (int e = tid; e < cn * 16; e += kContractThreads) {
-        const int o = rt * 16 + (e & 15), l = c0 + (e >> 4);
-        anc[e] = o < M ? shear_phase<LOG2N>((uint32_t)(kb * kBinBlock), shift[(size_t)o * L + l], fac)
-                       : make_float2(0.f, 0.f);
-    }
-}
-
-// Lane roles of v_mfma_f32_32x32x2_f32.  A (32 x 2): row lane % 32 = {Re rows 0..15, Im rows
-// 16..31} x 16 receive angles, column lane / 32 = {Re, Im} part of the element; the lane
-// supplies Wr (Re row, Re part), -Wi (Re row, Im part), Wi (Im row, Re part), Wr (Im, Im).
-// B (2 x 32): part lane / 32 of transmit column lane % 32.
-struct LaneRole {
-    int part, col, orow;
-    bool use_im;
-    uint32_t negmask;
-    __device__ __forceinline__ explicit LaneRole(int lane) {
-        part = lane >> 5;
-        col = lane & 31;
-        orow = col & 15;
-        const int ytype = col >> 4;
-        use_im = ytype != part;
-        negmask = (ytype == 0 && part == 1) ? 0x80000000u : 0u;
-    }
-    __device__ __forceinline__ float pick(float2 w) const {
-        return __uint_as_float(__float_as_uint(use_im ? w.y : w.x) ^ negmask);
-    }
-};
-
-// Operands of one element in flight: spectrum (bin 2p + part of this lane's transmit), anchor
-// phase of this lane's angle, phase steps {D_2p, D_1}.
+// Operands of one element in flight: spectrum (bins 2p, 2p+1 part of this lane's transmit: one
+// 8-byte piece of the 64-byte run), the phase coefficients of this lane for both bins, and the
+// anchor of this lane's angle.
 struct ElemLoads {
     float2 x;
+    float4 c;
     float2 a;
-    float4 d;
 };
 
 // Per bin block (8 bins), receive tile of 16 and transmit tile of 32:
-// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i].  W_{8kb+2p} = W_{8kb} D_2p and W_{8kb+2p+1} =
-// W_{8kb+2p} D_1 (two roundings from exactly evaluated factors).  The spectrum is read
-// straight from global memory: one 8-byte load per lane gives bins 2p (lanes 0..31 Re, 32..63
-// Im after one v_permlane32_swap) and 2p+1; no LDS staging and no barrier in the element loop.
-// Results leave through LDS as 64-byte runs (8 bins of one (i, o)).
-template <int LOG2N>
-__device__ __forceinline__ void contract_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
-                                              const float4* __restrict__ phd, float2* __restrict__ Y, int ntx,
+// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i].  Lane roles of v_mfma_f32_32x32x2_f32: A (32 x 2) row
+// lane % 32 = {Re rows 0..15, Im rows 16..31} x 16 angles, column lane / 32 = {Re, Im} part of
+// the element, so the lane supplies Re W, -Im W, Im W or Re W: with the anchor a from LDS and
+// the lane's coefficients c, Re(a) c.x + Im(a) c.y (bin 2p) and Re(a) c.z + Im(a) c.w (bin
+// 2p+1).  B (2 x 32): part lane / 32 of transmit column lane % 32; one 8-byte load per lane
+// gives bin 2p (lanes 0..31) or 2p+1 (lanes 32..63) of its column, and one v_permlane32_swap
+// turns the pair into the B operands of both bins.  Loads run kDepth elements ahead; no LDS
+// staging of the spectrum and no barrier in the element loop.  Results leave through LDS as
+// 64-byte runs (8 bins of one (i, o)).
+__device__ __forceinline__ void contract_body(const float2* __restrict__ X, const float4* __restrict__ cf,
+                                              const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
                                               int M, int L, int ncol, int kpad, int kb, int rt, int ct) {
-    constexpr int N = 1 << LOG2N;
-    __shared__ float2 fac[64 + N / 64];
     __shared__ __attribute__((aligned(16))) float2 buf[kBufFloat2];
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int p = wave & 3, h = wave >> 2;
-    const LaneRole R(lane);
-    build_phase_factors<LOG2N>(fac, tid);
+    const int nrt = (M + 15) / 16;
 
     floatx16 acc0, acc1;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
 
-    // element l of this lane's operands: spectrum X[spec_index(8 kb + 2p + part, l, 32 ct + col)],
-    // phase steps PhD[((rt 4 + p) L + l) 16 + orow]
-    const size_t xstride = (size_t)kBinBlock * ncol;
-    // padding columns past the last transmit (never written) read the last transmit's spectrum,
-    // whose lines are fetched anyway; their results are discarded
-    const int icol = min(ct * 32 + R.col, ntx - 1);
-    const float2* xp = X + spec_index(kb * kBinBlock + 2 * p, 0, icol, L, ncol) + R.part;
-    const float4* dp = phd + ((size_t)rt * 4 + p) * L * 16 + R.orow;
+    // element l of this lane's operands: spectrum at byte xlane of row
+    // X + spec_index(8 kb, l, 32 ct) (padding columns past the last transmit, never written,
+    // read the last transmit's run, whose lines are fetched anyway; their results are
+    // discarded), coefficients at float4 lane of row cf + ((rt 4 + p) L + l) 64
+    const int icol = min(ct * 32 + (lane & 31), ntx - 1) - ct * 32;
+    const uint32_t xlane = (uint32_t)icol * 64 + (uint32_t)(2 * p + (lane >> 5)) * 8;
+    const char* xblk = reinterpret_cast<const char*>(X + spec_index(kb * kBinBlock, 0, ct * 32, L, ncol));
+    const size_t xstride = (size_t)ncol * kBinBlock * sizeof(float2);
+    const uint32_t clane = (uint32_t)lane * sizeof(float4);
+    const char* cblk = reinterpret_cast<const char*>(cf + (size_t)(rt * 4 + p) * L * 64);
+    constexpr uint32_t cstride = 64 * sizeof(float4);
+    const float2* ablk = anc + ((size_t)kb * nrt + rt) * L * 16;
 
     for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
         const int cn = min(kAnchorChunk, L - c0);
-        __syncthreads();  // factor tables complete; the previous chunk's anchors consumed
-        build_anchors<LOG2N>(buf, fac, shift, kb, rt, M, L, c0, cn, tid);
-        __syncthreads();
         const int half = (cn + 1) >> 1;
         const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
         const int e1 = __builtin_amdgcn_readfirstlane(min(c0 + cn, e0 + half));
+        const int last = e1 - 1;
+        // this wave's anchor rows start at row0 (the second half after the first's zero rows)
+        const int row0 = h * (half + 2 * kDepth);
+        float4 av[kAnchorLoads];
+        if (c0) __syncthreads();  // the previous chunk's anchors consumed
+        anchor_load(av, ablk, c0, cn, tid);
+        // the chunk's spectrum rows and coefficient rows as buffer views (element l at byte
+        // (l - c0) xstride and (l - c0) cstride)
+        const __amdgpu_buffer_rsrc_t xv = buffer_view(xblk + (size_t)c0 * xstride, (uint32_t)(cn * xstride));
+        const __amdgpu_buffer_rsrc_t cv = buffer_view(cblk + (size_t)c0 * cstride, (uint32_t)cn * cstride);
+        auto xload = [&](int l) { return buffer_load2(xv, xlane, (uint32_t)(l - c0) * (uint32_t)xstride); };
+        auto cload = [&](int l) { return buffer_load4(cv, clane, (uint32_t)(l - c0) * cstride); };
+        ElemLoads q[kDepth];
         if (e0 < e1) {
-            // a whole number of kDepth-element steps; elements past the last one re-read it
-            // and enter with a zero phase
-            const int last = e1 - 1;
-            const int steps = (e1 - e0 + kDepth - 1) / kDepth;
-            ElemLoads q[kDepth];
+            // a whole number of kDepth-element steps; elements past the last one re-read its
+            // spectrum and coefficients and meet a zero anchor
 #pragma unroll
             for (int u = 0; u < kDepth; ++u) {
                 const int l = min(e0 + u, last);
-                q[u].x = xp[(size_t)l * xstride];
-                q[u].d = dp[(size_t)l * 16];
-                q[u].a = buf[(l - c0) * 16 + R.orow];
-                asm volatile("" ::: "memory");  // the prologue issues its loads in the loop's order
+                q[u].x = xload(l);
+                q[u].c = cload(l);
+                __builtin_amdgcn_sched_barrier(0);  // the prologue issues its loads in the loop's order
             }
+        }
+        anchor_store(av, buf, cn, half, 2 * kDepth, tid);
+        __syncthreads();
+        if (e0 < e1) {
+            const float2* arow = buf + row0 * 16 + (lane & 15);
+#pragma unroll
+            for (int u = 0; u < kDepth; ++u) q[u].a = arow[u * 16];
+            const int steps = (e1 - e0 + kDepth - 1) / kDepth;
             int e = e0;
-            for (int it = 0; it < steps; ++it, e += kDepth) {
+            for (int it = 0; it < steps; ++it, e += kDepth, arow += kDepth * 16) {
 #pragma unroll
                 for (int u = 0; u < kDepth; ++u) {
                     // operands of element e + u from the buffer ...
                     const ElemLoads& c = q[u];
-                    const float2 an = e + u <= last ? c.a : make_float2(0.f, 0.f);
                     const auto sw =
                         __builtin_amdgcn_permlane32_swap(__float_as_uint(c.x.x), __float_as_uint(c.x.y), false, false);
-                    const float2 w0 = cmul2(an, make_float2(c.d.x, c.d.y));
-                    const float2 w1 = cmul2(w0, make_float2(c.d.z, c.d.w));
-                    const float a0 = R.pick(w0), a1 = R.pick(w1);
+                    const float a0 = __builtin_fmaf(c.a.y, c.c.y, c.a.x * c.c.x);
+                    const float a1 = __builtin_fmaf(c.a.y, c.c.w, c.a.x * c.c.z);
                     // ... then the buffer takes the element kDepth ahead (into the same registers;
                     // the spectrum after the products that read its swapped copy)
                     const int ln = min(e + u + kDepth, last);
-                    q[u].d = dp[(size_t)ln * 16];
-                    q[u].a = buf[(ln - c0) * 16 + R.orow];
+                    q[u].c = cload(ln);
+                    q[u].a = arow[(u + kDepth) * 16];
                     acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, __uint_as_float(sw[0]), acc0, 0, 0, 0);
                     acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, __uint_as_float(sw[1]), acc1, 0, 0, 0);
-                    q[u].x = xp[(size_t)ln * xstride];
+                    __builtin_amdgcn_sched_barrier(0);  // the spectrum reload after both products
+                    q[u].x = xload(ln);
                     // keeps each element's refill loads in its own step (the loads stay kDepth
                     // steps ahead of their use instead of being moved next to it)
                     __builtin_amdgcn_sched_barrier(0);
@@ -224,11 +218,12 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
     // results to LDS as runs [i][o][bin], then out as 64-byte runs, 8 threads per run
     float2* yst = buf;
     if (h == 0) {
+        const int col = lane & 31;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
             const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            yst[R.col * kYCol + ol * kBinBlock + 2 * p] = make_float2(acc0[v], acc0[v + 8]);
-            yst[R.col * kYCol + ol * kBinBlock + 2 * p + 1] = make_float2(acc1[v], acc1[v + 8]);
+            yst[col * kYCol + ol * kBinBlock + 2 * p] = make_float2(acc0[v], acc0[v + 8]);
+            yst[col * kYCol + ol * kBinBlock + 2 * p + 1] = make_float2(acc1[v], acc1[v + 8]);
         }
     }
     __syncthreads();
@@ -289,27 +284,26 @@ __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
 }
 
 // Loads of one group of 8 elements for one lane: its 4 elements' spectra (bins 2p and 2p+1),
-// anchors and phase steps.
+// anchors and the coefficients of the lane that holds (Re row, Re part) of its angle:
+// (Re D, -Im D) of both bins.
 struct SplitLoads {
     float4 x[4];
     float2 a[4];
     float4 d[4];
 };
 
-template <int LOG2N, bool F16>
-__device__ __forceinline__ void contract_split_body(const float2* __restrict__ X, const int32_t* __restrict__ shift,
-                                                    const float4* __restrict__ phd, float2* __restrict__ Y, int ntx,
+template <bool F16>
+__device__ __forceinline__ void contract_split_body(const float2* __restrict__ X, const float4* __restrict__ cf,
+                                                    const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
                                                     int M, int L, int ncol, int kpad, float xscale, float yscale,
                                                     int kb, int rt, int ct) {
-    constexpr int N = 1 << LOG2N;
-    __shared__ float2 fac[64 + N / 64];
     __shared__ __attribute__((aligned(16))) float2 buf[kBufFloat2];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int p = wave & 3, h = wave >> 2;
     const int g = lane >> 5, col = lane & 31, orow = col & 15;
     const bool im_row = col >= 16;
-    build_phase_factors<LOG2N>(fac, tid);
+    const int nrt = (M + 15) / 16;
 
     floatx16 acc0, acc1;
 #pragma unroll
@@ -319,12 +313,17 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
     // padding columns read the last transmit's spectrum (results discarded)
     const float4* xp = reinterpret_cast<const float4*>(
         X + spec_index(kb * kBinBlock + 2 * p, 0, min(ct * 32 + col, ntx - 1), L, ncol));
-    const float4* dp = phd + ((size_t)rt * 4 + p) * L * 16 + orow;
+    const float4* dp = cf + (size_t)(rt * 4 + p) * L * 64 + orow;
+    const float2* ablk = anc + ((size_t)kb * nrt + rt) * L * 16;
 
     for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
         const int cn = min(kAnchorChunk, L - c0);
         __syncthreads();
-        build_anchors<LOG2N>(buf, fac, shift, kb, rt, M, L, c0, cn, tid);
+        {
+            float4 av[kAnchorLoads];
+            anchor_load(av, ablk, c0, cn, tid);
+            anchor_store(av, buf, cn, cn, 0, tid);
+        }
         __syncthreads();
         const int half = (cn + 1) >> 1;
         const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
@@ -335,7 +334,7 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
             for (int e = 0; e < 4; ++e) {
                 const int l = min(l0 + 4 * g + e, last);
                 q.x[e] = xp[(size_t)l * (xstride / 2)];
-                q.d[e] = dp[(size_t)l * 16];
+                q.d[e] = dp[(size_t)l * 64];
                 q.a[e] = buf[(l - c0) * 16 + orow];
             }
         };
@@ -360,8 +359,8 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
                     for (int k = 0; k < 4; ++k) {
                         const bool valid = l0 + 4 * g + k <= last;
                         const float2 an = valid ? c.a[k] : make_float2(0.f, 0.f);
-                        const float2 w0 = cmul2(an, make_float2(c.d[k].x, c.d[k].y));
-                        const float2 w1 = cmul2(w0, make_float2(c.d[k].z, c.d[k].w));
+                        const float2 w0 = cmul2(an, make_float2(c.d[k].x, -c.d[k].y));
+                        const float2 w1 = cmul2(an, make_float2(c.d[k].z, -c.d[k].w));
                         // A row pair: Re rows (Wr, -Wi), Im rows (Wi, Wr)
                         split_pair<F16>(im_row ? w0.y : w0.x, im_row ? w0.x : -w0.y, hv[0][k], hv[1][k]);
                         split_pair<F16>(im_row ? w1.y : w1.x, im_row ? w1.x : -w1.y, hv[2][k], hv[3][k]);
@@ -428,122 +427,88 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
     }
 }
 
-template <int LOG2N>
 __global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
-                                                                     const int32_t* __restrict__ shift,
-                                                                     const float4* __restrict__ phd,
+                                                                     const float4* __restrict__ cf,
+                                                                     const float2* __restrict__ anc,
                                                                      float2* __restrict__ Y, int ntx, int M,
                                                                      int L, int ncol, int kpad) {
-    contract_body<LOG2N>(X, shift, phd, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z);
+    contract_body(X, cf, anc, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-template <int LOG2N, bool F16>
+template <bool F16>
 __global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
-    const float2* __restrict__ X, const int32_t* __restrict__ shift, const float4* __restrict__ phd,
+    const float2* __restrict__ X, const float4* __restrict__ cf, const float2* __restrict__ anc,
     float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad, float xscale, float yscale) {
-    contract_split_body<LOG2N, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
-                                    blockIdx.z);
+    contract_split_body<F16>(X, cf, anc, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
+                             blockIdx.z);
 }
 
 // Grouped launches over the frames of one FFT-length class: block b runs block b - block0
 // of frame entry blk[b], in the per-frame grid order (bin block fastest, then receive tile,
 // then transmit tile).  PREC: 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo.
-template <int LOG2N, int PREC>
+template <int PREC>
 __global__ __launch_bounds__(kContractThreads) void contract_grouped(const ContractEntry* __restrict__ tab,
                                                                      const int32_t* __restrict__ blk,
-                                                                     float2* __restrict__ ws,
-                                                                     const int32_t* __restrict__ plan) {
+                                                                     float2* __restrict__ ws) {
     const ContractEntry e = tab[blk[blockIdx.x]];
     int local = (int)blockIdx.x - e.block0;
     const int kb = local % e.nkb;
     local /= e.nkb;
     const int rt = local % e.nrt, ct = local / e.nrt;
-    const float4* phd = reinterpret_cast<const float4*>(ws + e.d_off);
+    const PhaseTables pt{nullptr, e.M, reinterpret_cast<float4*>(ws + e.d_off)};
     if constexpr (PREC == 0)
-        contract_body<LOG2N>(ws + e.x_off, plan + e.shift_off, phd, ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad, kb,
-                             rt, ct);
+        contract_body(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct);
     else
-        contract_split_body<LOG2N, PREC == 2>(ws + e.x_off, plan + e.shift_off, phd, ws + e.y_off, e.ntx, e.M, e.L,
-                                              e.ncol, e.kpad, e.xscale, e.yscale, kb, rt, ct);
+        contract_split_body<PREC == 2>(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
+                                       e.xscale, e.yscale, kb, rt, ct);
 }
 
-template <int LOG2N>
-hipError_t grouped_contract(int prec, const ContractEntry* tab, const int32_t* blk, int blocks, float2* ws,
-                            const int32_t* plan, hipStream_t st) {
-    const dim3 g(blocks), b(kContractThreads);
-    switch (prec) {
-        case KK_PREC_FP32: hipLaunchKernelGGL((contract_grouped<LOG2N, 0>), g, b, 0, st, tab, blk, ws, plan); break;
-        case KK_PREC_BF16X3: hipLaunchKernelGGL((contract_grouped<LOG2N, 1>), g, b, 0, st, tab, blk, ws, plan); break;
-        case KK_PREC_FP16X3: hipLaunchKernelGGL((contract_grouped<LOG2N, 2>), g, b, 0, st, tab, blk, ws, plan); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int LOG2N, bool F16>
-hipError_t contract_split(const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx, int M, int L,
-                          int ncol, int kpad, float xscale, hipStream_t st) {
-    const dim3 grid((1 << LOG2N) / 2 / kBinBlock, (M + 15) / 16, ncol / 32);
-    hipLaunchKernelGGL((contract_split_kernel<LOG2N, F16>), grid, dim3(kContractThreads), 0, st, X, shift, phd, Y,
-                       ntx, M, L, ncol, kpad, xscale, 1.0f / xscale);
-    return hipGetLastError();
-}
-
-template <int LOG2N>
-hipError_t contract(const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx, int M, int L,
-                    int ncol, int kpad, hipStream_t st) {
-    // bins 0 .. n/2 - 1; the Nyquist bin is summed by the inverse transform
-    const dim3 grid((1 << LOG2N) / 2 / kBinBlock, (M + 15) / 16, ncol / 32);
-    hipLaunchKernelGGL((contract_kernel<LOG2N>), grid, dim3(kContractThreads), 0, st, X, shift, phd, Y, ntx, M, L,
-                       ncol, kpad);
-    return hipGetLastError();
-}
-
-template <bool F16>
-hipError_t launch_contract_split(int log2n, const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx,
-                                 int M, int L, int ncol, int kpad, float xscale, hipStream_t st) {
-    switch (log2n) {
-        case 8: return contract_split<8, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 9: return contract_split<9, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 10: return contract_split<10, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 11: return contract_split<11, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 12: return contract_split<12, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
-        case 13: return contract_split<13, F16>(X, shift, phd, Y, ntx, M, L, ncol, kpad, xscale, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_contract(int log2n, const float2* X, const int32_t* shift, const float4* phd, float2* Y, int ntx,
-                           int M, int L, int ncol, int kpad, hipStream_t st) {
-    switch (log2n) {
-        case 8: return contract<8>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
-        case 9: return contract<9>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
-        case 10: return contract<10>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
-        case 11: return contract<11>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
-        case 12: return contract<12>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
-        case 13: return contract<13>(X, shift, phd, Y, ntx, M, L, ncol, kpad, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+// bins 0 .. n/2 - 1 (the Nyquist bin is summed by the inverse transform)
+dim3 contract_grid(int log2n, int M, int ncol) { return dim3(contract_bin_blocks(log2n), (M + 15) / 16, ncol / 32); }
 
 }  // namespace
 
-hipError_t launch_contract_grouped(int log2n, int precision, const ContractEntry* tab, const int32_t* blk, int blocks,
-                                   float2* ws, const int32_t* plan, hipStream_t st) {
-    switch (log2n) {
-        case 8: return grouped_contract<8>(precision, tab, blk, blocks, ws, plan, st);
-        case 9: return grouped_contract<9>(precision, tab, blk, blocks, ws, plan, st);
-        case 10: return grouped_contract<10>(precision, tab, blk, blocks, ws, plan, st);
-        case 11: return grouped_contract<11>(precision, tab, blk, blocks, ws, plan, st);
-        case 12: return grouped_contract<12>(precision, tab, blk, blocks, ws, plan, st);
-        case 13: return grouped_contract<13>(precision, tab, blk, blocks, ws, plan, st);
+// FP32 or split-precision contraction of one frame; the phase tables sit at pt.cf.
+hipError_t launch_contract(int log2n, int precision, const float2* X, const PhaseTables& pt, float2* Y, int ntx,
+                           int L, int ncol, int kpad, float xscale, hipStream_t st) {
+    if (log2n < kMinLog2Fft || log2n > kMaxLog2Fft) return hipErrorInvalidValue;
+    const dim3 grid = contract_grid(log2n, pt.M, ncol), block(kContractThreads);
+    const float2* anc = pt.anc(L);
+    switch (precision) {
+        case KK_PREC_FP32:
+            hipLaunchKernelGGL(contract_kernel, grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L, ncol, kpad);
+            break;
+        case KK_PREC_BF16X3:
+            hipLaunchKernelGGL((contract_split_kernel<false>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
+                               ncol, kpad, xscale, 1.0f / xscale);
+            break;
+        case KK_PREC_FP16X3:
+            hipLaunchKernelGGL((contract_split_kernel<true>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
+                               ncol, kpad, xscale, 1.0f / xscale);
+            break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_grouped(int log2n, int precision, const ContractEntry* tab, const int32_t* blk, int blocks,
+                                   float2* ws, const int32_t* plan, hipStream_t st) {
+    (void)plan;
+    if (log2n < kMinLog2Fft || log2n > kMaxLog2Fft) return hipErrorInvalidValue;
+    const dim3 g(blocks), b(kContractThreads);
+    switch (precision) {
+        case KK_PREC_FP32: hipLaunchKernelGGL((contract_grouped<0>), g, b, 0, st, tab, blk, ws); break;
+        case KK_PREC_BF16X3: hipLaunchKernelGGL((contract_grouped<1>), g, b, 0, st, tab, blk, ws); break;
+        case KK_PREC_FP16X3: hipLaunchKernelGGL((contract_grouped<2>), g, b, 0, st, tab, blk, ws); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 namespace {
+
+constexpr size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
 // bins [from, kpad) of every record of y [n][kpad] set to zero
 __global__ void zero_bins_kernel(float2* __restrict__ y, int64_t n, int kpad, int from) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -568,7 +533,7 @@ struct DecomposeLayout {
     size_t x_off, d_off, y_off, total;
 };
 
-// workspace: spectra (contraction layout), phase steps, contracted spectra [N][M][kpad]
+// workspace: spectra (contraction layout), phase tables, contracted spectra [N][M][kpad]
 bool decompose_layout(const kk_geom* g, int32_t N, int32_t M, int32_t tpad, DecomposeLayout* d) {
     const int lg = log2_exact(tpad);
     if (lg < kMinLog2Fft || lg > kMaxLog2Fft || g->T < 1 || g->T > tpad || g->L < 1 || N < 1 || M < 1) return false;
@@ -578,25 +543,20 @@ bool decompose_layout(const kk_geom* g, int32_t N, int32_t M, int32_t tpad, Deco
     d->ncol = (N + 31) / 32 * 32;
     d->x_off = 0;
     d->d_off = d->x_off + align256((size_t)d->kpad * d->ncol * g->L * 8);
-    d->y_off = d->d_off + align256(phase_step_floats4(M, g->L) * 16);
+    d->y_off = d->d_off + align256(phase_table_bytes(M, g->L, lg));
     d->total = d->y_off + align256((size_t)N * M * d->kpad * 8);
     return true;
 }
 
-// Forward transform (with the phase steps) and the per-bin contraction of one frame into Y.
+// Forward transform (with the phase tables) and the per-bin contraction of one frame into Y.
 hipError_t decompose_front(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M,
                            int32_t precision, const DecomposeLayout& d, unsigned char* w, float2* Y, hipStream_t st) {
     float2* X = reinterpret_cast<float2*>(w + d.x_off);
-    float4* phd = reinterpret_cast<float4*>(w + d.d_off);
-    const PhaseSteps ph{shift_q, M, phd};
-    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st, &ph);
+    const PhaseTables pt{shift_q, M, reinterpret_cast<float4*>(w + d.d_off)};
+    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st, &pt);
     if (e != hipSuccess) return e;
-    if (precision == KK_PREC_FP32)
-        return launch_contract(d.log2n, X, shift_q, phd, Y, N, M, g->L, d.ncol, d.kpad, st);
-    if (precision == KK_PREC_BF16X3)
-        return launch_contract_split<false>(d.log2n, X, shift_q, phd, Y, N, M, g->L, d.ncol, d.kpad, 1.0f, st);
-    return launch_contract_split<true>(d.log2n, X, shift_q, phd, Y, N, M, g->L, d.ncol, d.kpad,
-                                       std::ldexp(1.0f, fp16_prescale_exponent(g->T)), st);
+    const float xscale = precision == KK_PREC_FP16X3 ? std::ldexp(1.0f, fp16_prescale_exponent(g->T)) : 1.0f;
+    return launch_contract(d.log2n, precision, X, pt, Y, N, g->L, d.ncol, d.kpad, xscale, st);
 }
 
 struct DasLayout {

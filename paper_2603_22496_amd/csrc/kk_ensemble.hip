@@ -167,7 +167,7 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
         in.rf_theta_offset = ws / 8;
         ws = align_up(ws + (int64_t)fr.N * fr.M * g.T * 8, 256);
         w.x_bytes = align_up((int64_t)w.kpad * w.ncol * g.L * 8, 256);
-        w.d_bytes = align_up((int64_t)phase_step_floats4(fr.M, g.L) * 16, 256);
+        w.d_bytes = align_up((int64_t)phase_table_bytes(fr.M, g.L, w.log2n), 256);
         w.y_bytes = align_up((int64_t)fr.N * fr.M * w.kpad * 8, 256);
     }
     for (int f = 0; f < nf; ++f) {
@@ -246,8 +246,8 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
                 a.ncol = w.ncol;
                 a.kpad = w.kpad;
                 a.block0 = (int32_t)fb.size();
-                // record pairs (transmits i, i+1 of one element), then the phase-step blocks
-                const int64_t nfb = (int64_t)in.L * ((in.N + 1) / 2) + phase_step_blocks(in.M, in.L, lg);
+                // record pairs (transmits i, i+1 of one element), then the phase-table blocks
+                const int64_t nfb = (int64_t)in.L * ((in.N + 1) / 2) + phase_table_blocks(in.M, in.L, lg);
                 if (!check_blocks((int64_t)fb.size() + nfb)) return KK_E_ARG;
                 fb.insert(fb.end(), (size_t)nfb, e);
                 fe.push_back(a);

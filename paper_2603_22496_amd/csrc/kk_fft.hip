@@ -233,39 +233,71 @@ __device__ __forceinline__ void middle_passes(float2* data, const float2* fac, i
     }
 }
 
-// The contraction's per-element phase steps (extra workgroups of a blocked forward launch):
-// thread e of phase block b handles entry (rt, l, o % 16) = e-th of nrt x L x 16 and writes
-// {D_2p, D_1} for p = 0..3.  Each D_j is evaluated from the exact integer turn count
-// (j shift) mod (n 2^22) in FP64 and rounded once to FP32.
+// exp(2 pi i ((k s) mod (n 2^22)) / (n 2^22)): the turn count reduced exactly in integers, the
+// angle in FP64, rounded once to FP32.
 template <int LOG2N>
-__device__ __forceinline__ void phase_step_block(const int32_t* __restrict__ shift, int M, int L,
-                                                 float4* __restrict__ phd, int b) {
+__device__ __forceinline__ float2 exact_turn(int64_t k, int64_t s) {
+    constexpr int64_t period = (int64_t)1 << (LOG2N + 22);
+    int64_t r = (k * s) % period;
+    if (r < 0) r += period;
+    double sn, cs;
+    sincospi((double)r / (double)(period >> 1), &sn, &cs);
+    return make_float2((float)cs, (float)sn);
+}
+
+// The contraction's phase tables (extra workgroups of a blocked forward launch; the layouts
+// are those of PhaseTables).  Work item e of table block b: a coefficient entry (rt, l, o % 16)
+// (D_1 .. D_7 of its angle and element, expanded into its four operand lanes for p = 0..3), or
+// four anchors W_{8 kb}[o][l] of consecutive angles.
+template <int LOG2N>
+__device__ __forceinline__ void phase_table_block(const int32_t* __restrict__ shift, int M, int L,
+                                                  float4* __restrict__ cf, float2* __restrict__ anc, int b) {
+    constexpr int nkb = (1 << LOG2N) / 2 / kBinBlock;
     const int nrt = (M + 15) / 16;
     const int64_t e = (int64_t)b * fft_threads<LOG2N>() + threadIdx.x;
-    if (e >= (int64_t)nrt * L * 16) return;
-    const int oo = (int)(e & 15);
-    const int64_t rl = e >> 4;
-    const int l = (int)(rl % L), rt = (int)(rl / L);
-    const int o = rt * 16 + oo;
-    float2 d[7];
+    const int64_t ncf = (int64_t)nrt * L * 16;
+    if (e < ncf) {
+        const int o16 = (int)(e & 15);
+        const int64_t rl = e >> 4;
+        const int l = (int)(rl % L), rt = (int)(rl / L);
+        const int o = rt * 16 + o16;
+        float2 d[8];
+        if (o < M) {
+            const int64_t s = shift[(size_t)o * L + l];
+            d[0] = make_float2(1.f, 0.f);
 #pragma unroll
-    for (int j = 0; j < 7; ++j) d[j] = make_float2(1.f, 0.f);
-    if (o < M) {
-        constexpr int64_t period = (int64_t)1 << (LOG2N + 22);
-        const int64_t s = shift[(size_t)o * L + l];
+            for (int j = 1; j < 8; ++j) d[j] = exact_turn<LOG2N>(j, s);
+        } else {
 #pragma unroll
-        for (int j = 1; j < 7; ++j) {
-            if (j != 1 && (j & 1)) continue;  // D_1, D_2, D_4, D_6
-            int64_t r = (j * s) % period;
-            if (r < 0) r += period;
-            double sn, cs;
-            sincospi(2.0 * (double)r / (double)period, &sn, &cs);
-            d[j] = make_float2((float)cs, (float)sn);
+            for (int j = 0; j < 8; ++j) d[j] = make_float2(0.f, 0.f);
         }
-    }
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-        phd[(((size_t)rt * 4 + p) * L + l) * 16 + oo] = make_float4(d[2 * p].x, d[2 * p].y, d[1].x, d[1].y);
+        for (int p = 0; p < 4; ++p) {
+            const float2 u = d[2 * p], v = d[2 * p + 1];
+            float4* row = cf + (((size_t)rt * 4 + p) * L + l) * 64;
+            row[o16] = make_float4(u.x, -u.y, v.x, -v.y);        // Re row, Re part: Re W
+            row[o16 + 16] = make_float4(u.y, u.x, v.y, v.x);     // Im row, Re part: Im W
+            row[o16 + 32] = make_float4(-u.y, -u.x, -v.y, -v.x); // Re row, Im part: -Im W
+            row[o16 + 48] = make_float4(u.x, -u.y, v.x, -v.y);   // Im row, Im part: Re W
+        }
+        return;
+    }
+    const int64_t a = e - ncf;
+    if (a >= (int64_t)nkb * nrt * L * 4) return;
+    const int quad = (int)(a & 3);
+    int64_t r = a >> 2;
+    const int l = (int)(r % L);
+    r /= L;
+    const int rt = (int)(r % nrt), kb = (int)(r / nrt);
+    float2 w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int o = rt * 16 + quad * 4 + q;
+        w[q] = o < M ? exact_turn<LOG2N>((int64_t)kb * kBinBlock, shift[(size_t)o * L + l]) : make_float2(0.f, 0.f);
+    }
+    float4* dst = reinterpret_cast<float4*>(anc + ((((size_t)kb * nrt + rt) * L + l) * 16 + quad * 4));
+    dst[0] = make_float4(w[0].x, w[0].y, w[1].x, w[1].y);
+    dst[1] = make_float4(w[2].x, w[2].y, w[3].x, w[3].y);
 }
 
 // One record pair per workgroup: the two real records are the real and imaginary parts of one
@@ -274,11 +306,11 @@ __device__ __forceinline__ void phase_step_block(const int32_t* __restrict__ shi
 // leave as whole 128-byte lines (8 bins of both records, four threads); trace layout:
 // records 2 blk, 2 blk + 1, and 64-byte runs (8 bins) of each record.
 // Body of block blk of one frame (shared by the per-frame and the grouped launches); blocked
-// launches carry the phase-step blocks after the record pairs.
+// launches carry the phase-table blocks after the record pairs.
 template <int LOG2N, bool BLOCKED>
 __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf, int ntraces, int T,
                                                  float2* __restrict__ out, int L, int ncol, int kpad, int blk,
-                                                 const int32_t* __restrict__ shift, int M, float4* __restrict__ phd) {
+                                                 const int32_t* __restrict__ shift, int M, float4* __restrict__ cf) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
     __shared__ __attribute__((aligned(16))) float2 data[N + N / 16];
@@ -290,7 +322,7 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
         const int ntx = ntraces / L;
         const int npairs = (ntx + 1) / 2;
         if (blk >= L * npairs) {  // uniform per workgroup, before any barrier
-            if (phd) phase_step_block<LOG2N>(shift, M, L, phd, blk - L * npairs);
+            if (cf) phase_table_block<LOG2N>(shift, M, L, cf, PhaseTables{shift, M, cf}.anc(L), blk - L * npairs);
             return;
         }
         l0 = blk % L;
@@ -473,8 +505,8 @@ template <int LOG2N, bool BLOCKED>
 __global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
                                                                   int T, float2* __restrict__ out, int L, int ncol,
                                                                   int kpad, const int32_t* __restrict__ shift, int M,
-                                                                  float4* __restrict__ phd) {
-    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x, shift, M, phd);
+                                                                  float4* __restrict__ cf) {
+    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x, shift, M, cf);
 }
 
 template <int LOG2N, bool NYQ>
@@ -510,14 +542,14 @@ __global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_inverse_grouped(cons
 
 template <int LOG2N>
 hipError_t fwd(const int16_t* rf, int ntraces, int T, float2* out, bool blocked, int L, int ncol, int kpad,
-               hipStream_t st, const PhaseSteps* ph) {
+               hipStream_t st, const PhaseTables* ph) {
     if (blocked) {
-        // one record pair (transmits i, i+1 of one element) per workgroup, then the phase steps
+        // one record pair (transmits i, i+1 of one element) per workgroup, then the phase tables
         const int64_t pairs = (int64_t)L * ((ntraces / L + 1) / 2);
-        const int64_t pblocks = ph ? phase_step_blocks(ph->M, L, LOG2N) : 0;
+        const int64_t pblocks = ph ? phase_table_blocks(ph->M, L, LOG2N) : 0;
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3((unsigned)(pairs + pblocks)), dim3(fft_threads<LOG2N>()), 0,
                            st, rf, ntraces, T, out, L, ncol, kpad, ph ? ph->shift : nullptr, ph ? ph->M : 0,
-                           ph ? ph->phd : nullptr);
+                           ph ? ph->cf : nullptr);
     } else {
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, false>), dim3((ntraces + 1) / 2), dim3(fft_threads<LOG2N>()), 0, st, rf,
                            ntraces, T, out, L, ncol, kpad, nullptr, 0, nullptr);
@@ -539,7 +571,7 @@ hipError_t inv(const float2* in, int ntraces, int kpad, float2* out, int T, hipS
 }  // namespace
 
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
-                              int ncol, int kpad, hipStream_t st, const PhaseSteps* ph) {
+                              int ncol, int kpad, hipStream_t st, const PhaseTables* ph) {
     switch (log2n) {
         case 8: return fwd<8>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
         case 9: return fwd<9>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);

@@ -19,23 +19,49 @@ __host__ __device__ inline size_t spec_index(int k, int l, int i, int L, int nco
     return (((size_t)(k >> 3) * L + l) * ncol + i) * 8 + (k & 7);
 }
 
-// Per-element phase steps of the contraction, D_j[o][l] = exp(2 pi i ((j shift[o][l]) mod (n 2^22))
-// / (n 2^22)) (n the FFT length): float4 {D_2p, D_1} at PhD[((rt 4 + p) L + l) 16 + o % 16],
-// rt = o / 16, p = 0..3; rows o >= M hold D = 1.  Written by the forward FFT launch.
-inline size_t phase_step_floats4(int M, int L) { return (size_t)((M + 15) / 16) * 4 * (size_t)L * 16; }
+// Phase tables of the contraction, written by the extra workgroups of a blocked forward launch
+// (nrt = receive tiles of 16 angles, nkb = n / 16 bin blocks; rows o >= M are zero):
+//   coefficients Cf[((rt 4 + p) L + l) 64 + lane] (float4), for lane = the lane of the FP32
+//     contraction's MFMA operand A: row r = lane % 32 (Re rows r < 16, Im rows r >= 16, angle
+//     o = 16 rt + r % 16) and element part q = lane / 32; (x, y) for bin offset j = 2p and (z, w)
+//     for j = 2p + 1 are chosen so that the operand is Re(a) x + Im(a) y for the bin block's
+//     anchor a: (Re D_j, -Im D_j) for (Re row, Re part) and (Im row, Im part), (Im D_j, Re D_j) for
+//     (Im row, Re part), (-Im D_j, -Re D_j) for (Re row, Im part), where
+//     D_j[o][l] = exp(2 pi i ((j shift[o][l]) mod (n 2^22)) / (n 2^22));
+//   anchors Anc[((kb nrt + rt) L + l) 16 + o % 16] (float2) = W_{8 kb}[o][l], the Eq. 3 phase of
+//     the first bin of block kb.
+// The anchor times the step of the bin's offset in its block gives the bin's phase.
+__host__ __device__ inline int contract_bin_blocks(int log2n) { return (1 << log2n) / 2 / kBinBlock; }
+__host__ __device__ inline size_t phase_cf_floats4(int M, int L) {
+    return (size_t)((M + 15) / 16) * 4 * (size_t)L * 64;
+}
+__host__ __device__ inline size_t phase_anc_floats2(int M, int L, int log2n) {
+    return (size_t)contract_bin_blocks(log2n) * ((M + 15) / 16) * (size_t)L * 16;
+}
+inline size_t phase_table_bytes(int M, int L, int log2n) {
+    return phase_cf_floats4(M, L) * 16 + phase_anc_floats2(M, L, log2n) * 8;
+}
 
 // Threads per workgroup of the FFT kernels for a transform of 2^log2n points.
 constexpr int fft_threads_for(int log2n) { return log2n >= 13 ? 512 : 256; }
-// Workgroups of a blocked forward launch that write the phase steps (after the record pairs).
-inline int64_t phase_step_blocks(int M, int L, int log2n) {
+// Work items of the phase tables: one per (rt, l, o % 16) coefficient entry (its four lanes, all
+// p), then one per four anchors (kb, rt, l, o % 16 / 4).
+inline int64_t phase_table_items(int M, int L, int log2n) {
+    const int64_t nrt = (M + 15) / 16;
+    return nrt * L * 16 + (int64_t)contract_bin_blocks(log2n) * nrt * L * 4;
+}
+// Workgroups of a blocked forward launch that write the phase tables (after the record pairs).
+inline int64_t phase_table_blocks(int M, int L, int log2n) {
     const int64_t t = fft_threads_for(log2n);
-    return ((int64_t)phase_step_floats4(M, L) / 4 + t - 1) / t;
+    return (phase_table_items(M, L, log2n) + t - 1) / t;
 }
 
-struct PhaseSteps {
+// Where a blocked forward launch writes the phase tables: Cf at base, Anc right after it.
+struct PhaseTables {
     const int32_t* shift;  // [M][L] Q.22 advances
     int M;
-    float4* phd;           // out, phase_step_floats4(M, L) entries
+    float4* cf;            // phase_cf_floats4(M, L) entries, then phase_anc_floats2(M, L, log2n) anchors
+    __host__ __device__ float2* anc(int L) const { return reinterpret_cast<float2*>(cf + phase_cf_floats4(M, L)); }
 };
 
 constexpr int kMinLog2Fft = 8;
@@ -54,10 +80,10 @@ inline int log2_exact(int64_t n) {
 //   blocked: out[spec_index(k, l, i, L, ncol)] for record t = i L + l (contraction layout;
 //            records i and i+1 of element l share a workgroup, a missing partner record of
 //            an odd transmit count is written as zeros); the launch also writes the phase
-//            steps *ph of the contraction (extra workgroups), when ph is given
+//            tables *ph of the contraction (extra workgroups), when ph is given
 //   else:    out[t * kpad + k]                                   (trace layout)
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
-                              int ncol, int kpad, hipStream_t st, const PhaseSteps* ph = nullptr);
+                              int ncol, int kpad, hipStream_t st, const PhaseTables* ph = nullptr);
 
 // Where the Nyquist bin of record t = i * M + o is not stored but summed by the inverse
 // transform itself: Y[n/2] = sum_l exp(i pi shift[o][l] / 2^22) X[i][l][n/2] (Eq. 3 at k = n/2),
@@ -93,13 +119,13 @@ int fp16_prescale_exponent(int T);
 struct FwdEntry {
     int64_t rf_off;          // channel data of the frame, [N][L][T]
     int64_t x_off;           // workspace: analytic spectra in the contraction layout
-    int64_t d_off;           // workspace: phase steps of the contraction (float2 units)
+    int64_t d_off;           // workspace: phase tables of the contraction (float2 units)
     int32_t ntraces, T, L, ncol, kpad, block0;
     int32_t shift_off, M;    // plan: shift table [M][L]
 };
 struct ContractEntry {
     int64_t x_off, y_off;    // workspace: spectra in, contracted spectra [N][M][kpad] out
-    int64_t d_off;           // workspace: phase steps (float2 units)
+    int64_t d_off;           // workspace: phase tables (float2 units)
     int32_t shift_off;       // plan: shift table [M][L]
     int32_t ntx, M, L, ncol, kpad, nkb, nrt, block0;
     float xscale, yscale;    // split-precision prescale and its inverse
