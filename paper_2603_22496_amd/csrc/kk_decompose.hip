@@ -26,25 +26,29 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// Contraction workgroup: one block of 8 bins, 16 receive angles, 32 transmit columns; wave w
-// takes the bin pair p = w % 4 (bins 8 kb + 2p, 8 kb + 2p + 1) over half h = w / 4 of the
-// elements, and the two halves are summed at the end.
+// FP32 contraction workgroup: one block of 8 bins, R8 tiles of 8 receive angles (R8 = 1 when
+// M <= 8, else 2: 16 angles), 32 transmit columns; wave w takes column group g = w % 2 (16
+// transmits) and element quarter e4 = w / 2 (element pairs 2j, 2j+1 with j = e4 (mod 4)), all 8
+// bins; the quarters are summed at the end in a fixed order.
 constexpr int kContractWaves = 8;
 constexpr int kContractThreads = kContractWaves * 64;
-// Elements whose anchors sit in LDS at once.
+// Element pairs whose operand loads are in flight per wave.
+constexpr int kDepth = 4;
+// Result staging: per transmit column, 16 angles x 8 bins x {Re, Im} floats and a pad of two
+// (the 16 columns of a wave's row then fall in distinct banks).
+constexpr int kYColF = 16 * kBinBlock * 2 + 2;
+constexpr int kStageFloat2 = 32 * kYColF / 2;
+
+// Split-precision workgroup: the same tile; wave w takes bin pair w % 4 over half w / 4 of the
+// elements, the halves summed at the end, with the chunk's anchors staged in LDS.
+constexpr int kSplitWaves = 8;
+constexpr int kSplitThreads = kSplitWaves * 64;
 constexpr int kAnchorChunk = 256;
-// Elements whose operand loads are in flight per wave.
-constexpr int kDepth = 8;
-// Anchor rows in LDS: each half of a chunk is followed by 2 kDepth zero rows, which the
-// software pipeline reads past the half's last element (those elements enter with zero phase).
-constexpr int kAnchorRows = kAnchorChunk + 4 * kDepth;
-// Result staging per transmit column: 16 angles x 8 bins and a pad (a half-wave's 32 columns
-// then write 64 distinct banks).
-constexpr int kYCol = 16 * kBinBlock + 1;
-constexpr int kBufFloat2 = kAnchorRows * 16 > 32 * kYCol ? kAnchorRows * 16 : 32 * kYCol;
-static_assert(kBufFloat2 >= 4096, "LDS buffer holds the half sums");
+constexpr int kYCol = 16 * kBinBlock + 1;  // split kernel's staging: float2 per (column, angle, bin) + pad
+constexpr int kSplitBuf = kAnchorChunk * 16 > 32 * kYCol ? kAnchorChunk * 16 : 32 * kYCol;
+static_assert(kSplitBuf >= 4096, "LDS buffer holds the half sums");
 // Anchor loads per thread of one chunk (16-byte pieces, 8 per element).
-constexpr int kAnchorLoads = (kAnchorChunk * 8 + kContractThreads - 1) / kContractThreads;
+constexpr int kAnchorLoads = (kAnchorChunk * 8 + kSplitThreads - 1) / kSplitThreads;
 
 __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -63,177 +67,232 @@ __device__ __forceinline__ float4 buffer_load4(__amdgpu_buffer_rsrc_t r, uint32_
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)lane_off, (int)off, 0));
 }
 
-// Anchors of elements [c0, c0 + cn) of one bin block and receive tile: global -> registers
-// (issued first, so that the caller's operand loads overlap them; indexes past the chunk
-// re-read its last piece) ...
-__device__ __forceinline__ void anchor_load(float4 (&v)[kAnchorLoads], const float2* __restrict__ anc, int c0, int cn,
-                                            int tid) {
+// Anchors of elements [c0, c0 + cn) of one bin block and receive tile (split kernel): global ->
+// registers -> LDS rows [l - c0][16] (indexes past the chunk re-read its last piece).
+__device__ __forceinline__ void stage_anchors(float2* buf, const float2* __restrict__ anc, int c0, int cn, int tid) {
     const float4* src = reinterpret_cast<const float4*>(anc) + (size_t)c0 * 8;
+    float4 v[kAnchorLoads];
 #pragma unroll
-    for (int u = 0; u < kAnchorLoads; ++u) v[u] = src[min(tid + u * kContractThreads, cn * 8 - 1)];
-}
-// ... -> LDS rows: element c0 + r at row r + (r >= split ? gap : 0); the gap rows after each
-// part are zero.
-__device__ __forceinline__ void anchor_store(const float4 (&v)[kAnchorLoads], float2* buf, int cn, int split, int gap,
-                                             int tid) {
+    for (int u = 0; u < kAnchorLoads; ++u) v[u] = src[min(tid + u * kSplitThreads, cn * 8 - 1)];
     float4* dst = reinterpret_cast<float4*>(buf);
 #pragma unroll
     for (int u = 0; u < kAnchorLoads; ++u) {
-        const int f = tid + u * kContractThreads;
-        if (f < cn * 8) dst[f + (f >= split * 8 ? gap * 8 : 0)] = v[u];
-    }
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int f = tid; f < gap * 8; f += kContractThreads) {
-        dst[split * 8 + f] = z;
-        dst[(cn + gap) * 8 + f] = z;
+        const int f = tid + u * kSplitThreads;
+        if (f < cn * 8) dst[f] = v[u];
     }
 }
 
-// Operands of one element in flight: spectrum (bins 2p, 2p+1 part of this lane's transmit: one
-// 8-byte piece of the 64-byte run), the phase coefficients of this lane for both bins, and the
-// anchor of this lane's angle.
-struct ElemLoads {
-    float2 x;
-    float4 c;
-    float2 a;
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Operands of one element pair in flight for one lane: spectrum bins 4q .. 4q+3 of its element
+// and transmit (q = its part, 32 bytes), and for each 8-angle tile the anchor and (D_1, D_4) of
+// its angle and element.
+template <int R8>
+struct PairLoads {
+    float4 x0, x1;
+    float2 a[R8];
+    float4 d[R8];
 };
 
-// Per bin block (8 bins), receive tile of 16 and transmit tile of 32:
-// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i].  Lane roles of v_mfma_f32_32x32x2_f32: A (32 x 2) row
-// lane % 32 = {Re rows 0..15, Im rows 16..31} x 16 angles, column lane / 32 = {Re, Im} part of
-// the element, so the lane supplies Re W, -Im W, Im W or Re W: with the anchor a from LDS and
-// the lane's coefficients c, Re(a) c.x + Im(a) c.y (bin 2p) and Re(a) c.z + Im(a) c.w (bin
-// 2p+1).  B (2 x 32): part lane / 32 of transmit column lane % 32; one 8-byte load per lane
-// gives bin 2p (lanes 0..31) or 2p+1 (lanes 32..63) of its column, and one v_permlane32_swap
-// turns the pair into the B operands of both bins.  Loads run kDepth elements ahead; no LDS
-// staging of the spectrum and no barrier in the element loop.  Results leave through LDS as
-// 64-byte runs (8 bins of one (i, o)).
-__device__ __forceinline__ void contract_body(const float2* __restrict__ X, const float4* __restrict__ cf,
+// Per bin block (8 bins), R8 x 8 receive angles and 32 transmit columns:
+// Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] on v_mfma_f32_16x16x4_f32, one instruction per bin,
+// 8-angle tile and element pair: A (16 x 4) row lane % 16 = {Re rows 0..7, Im rows 8..15} x 8
+// angles, column lane / 16 = (element e = lane / 32 of the pair, part q = lane / 16 % 2); B
+// (4 x 16) row lane / 16 = (e, q), column lane % 16 = transmit; C: lane holds rows
+// 4 (lane / 16) + 0..3 of column lane % 16.
+//  * Spectrum: each lane loads the 32-byte half run (bins 4q .. 4q+3) of its element and
+//    transmit, so a wave reads whole 64-byte runs (16 transmits x 2 elements, 2 KB); one
+//    v_permlane16_swap per bin pair (b, b+4) exchanges the halves into the B operands.
+//  * Phase: the lane needs one component of W_b for b = 0..7: Re W for (Re row, Re part) and
+//    (Im row, Im part), -Im W for (Re row, Im part), Im W for (Im row, Re part), i.e.
+//    Re(a' D_b) with a' = a, i a or -i a for the anchor a; D_b = D_1^b (b <= 3) or
+//    D_4 D_1^(b-4) (three products at most past the anchor).
+//  * Elements past the last one re-read its spectrum and steps; their anchors lie past the end
+//    of the anchor view, whose loads then return zero (the element offset is in the
+//    bounds-checked vector offset).
+// LDS floats of the contraction: partial sums of the element quarters (four wave slots), then
+// the result staging.
+template <int R8>
+constexpr int contract_lds_floats() { return R8 * 8192 > 32 * kYColF ? R8 * 8192 : 32 * kYColF; }
+
+template <int R8>
+__device__ __forceinline__ void contract_body(const float2* __restrict__ X, const float4* __restrict__ d14,
                                               const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
-                                              int M, int L, int ncol, int kpad, int kb, int rt, int ct) {
-    __shared__ __attribute__((aligned(16))) float2 buf[kBufFloat2];
+                                              int M, int L, int ncol, int kpad, int kb, int rt, int ct,
+                                              float* __restrict__ lds) {
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int p = wave & 3, h = wave >> 2;
+    const int g = wave & 1, e4 = wave >> 1;
     const int nrt = (M + 15) / 16;
 
-    floatx16 acc0, acc1;
+    floatx4 acc[R8][kBinBlock];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
+    for (int t = 0; t < R8; ++t)
+#pragma unroll
+        for (int b = 0; b < kBinBlock; ++b) acc[t][b] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // element l of this lane's operands: spectrum at byte xlane of row
-    // X + spec_index(8 kb, l, 32 ct) (padding columns past the last transmit, never written,
-    // read the last transmit's run, whose lines are fetched anyway; their results are
-    // discarded), coefficients at float4 lane of row cf + ((rt 4 + p) L + l) 64
-    const int icol = min(ct * 32 + (lane & 31), ntx - 1) - ct * 32;
-    const uint32_t xlane = (uint32_t)icol * 64 + (uint32_t)(2 * p + (lane >> 5)) * 8;
-    const char* xblk = reinterpret_cast<const char*>(X + spec_index(kb * kBinBlock, 0, ct * 32, L, ncol));
+    // lane roles
+    const int e = lane >> 5, q = (lane >> 4) & 1, rowtype = (lane >> 3) & 1, o8 = lane & 7;
+    const int icol = min(ct * 32 + g * 16 + (lane & 15), ntx - 1) - ct * 32;
+    // element l of this lane's operands: spectrum at byte xlane + l xstride of
+    // X + spec_index(8 kb, 0, 32 ct) (padding columns past the last transmit, never written, read
+    // the last transmit's run; their results are discarded); steps at byte dlane + 256 t + 256 l
+    // of D14 + rt L 16; anchor at byte alane + 64 t + 128 l of Anc + (kb nrt + rt) L 16
+    const uint32_t xlane = (uint32_t)icol * 64 + (uint32_t)q * 32;
+    const uint32_t dlane = (uint32_t)o8 * sizeof(float4) + (uint32_t)e * 256;  // + the pair's element
+    const uint32_t alane = (uint32_t)o8 * sizeof(float2);
     const size_t xstride = (size_t)ncol * kBinBlock * sizeof(float2);
-    const uint32_t clane = (uint32_t)lane * sizeof(float4);
-    const char* cblk = reinterpret_cast<const char*>(cf + (size_t)(rt * 4 + p) * L * 64);
-    constexpr uint32_t cstride = 64 * sizeof(float4);
-    const float2* ablk = anc + ((size_t)kb * nrt + rt) * L * 16;
-
-    for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
-        const int cn = min(kAnchorChunk, L - c0);
-        const int half = (cn + 1) >> 1;
-        const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
-        const int e1 = __builtin_amdgcn_readfirstlane(min(c0 + cn, e0 + half));
-        const int last = e1 - 1;
-        // this wave's anchor rows start at row0 (the second half after the first's zero rows)
-        const int row0 = h * (half + 2 * kDepth);
-        float4 av[kAnchorLoads];
-        if (c0) __syncthreads();  // the previous chunk's anchors consumed
-        anchor_load(av, ablk, c0, cn, tid);
-        // the chunk's spectrum rows and coefficient rows as buffer views (element l at byte
-        // (l - c0) xstride and (l - c0) cstride)
-        const __amdgpu_buffer_rsrc_t xv = buffer_view(xblk + (size_t)c0 * xstride, (uint32_t)(cn * xstride));
-        const __amdgpu_buffer_rsrc_t cv = buffer_view(cblk + (size_t)c0 * cstride, (uint32_t)cn * cstride);
-        auto xload = [&](int l) { return buffer_load2(xv, xlane, (uint32_t)(l - c0) * (uint32_t)xstride); };
-        auto cload = [&](int l) { return buffer_load4(cv, clane, (uint32_t)(l - c0) * cstride); };
-        ElemLoads q[kDepth];
-        if (e0 < e1) {
-            // a whole number of kDepth-element steps; elements past the last one re-read its
-            // spectrum and coefficients and meet a zero anchor
+    const __amdgpu_buffer_rsrc_t xv =
+        buffer_view(X + spec_index(kb * kBinBlock, 0, ct * 32, L, ncol), (uint32_t)(L * xstride));
+    const __amdgpu_buffer_rsrc_t dv = buffer_view(d14 + (size_t)rt * L * 16, (uint32_t)L * 256);
+    const __amdgpu_buffer_rsrc_t av = buffer_view(anc + ((size_t)kb * nrt + rt) * L * 16, (uint32_t)L * 128);
+    const int last = L - 1;
+    const uint32_t xlane_e = xlane + (uint32_t)e * (uint32_t)xstride;  // + the pair's element
+    // pair j = elements 2j, 2j + 1 (lanes of element 1 one row further); pairs past the end
+    // re-read the last element and the row after it (the next bin block's first row, or for the
+    // last block the Nyquist block; the next table row), which the zero anchor of an element
+    // past the last one cancels: anchors are read with the element in the bounds-checked vector
+    // offset of their view, so that reads past it return zero
+    auto load_phase = [&](PairLoads<R8>& d, int j) {
+        const uint32_t r = (uint32_t)min(2 * j, last);
 #pragma unroll
-            for (int u = 0; u < kDepth; ++u) {
-                const int l = min(e0 + u, last);
-                q[u].x = xload(l);
-                q[u].c = cload(l);
-                __builtin_amdgcn_sched_barrier(0);  // the prologue issues its loads in the loop's order
-            }
+        for (int t = 0; t < R8; ++t) {
+            d.d[t] = buffer_load4(dv, dlane + 128 * t, r * 256);
+            d.a[t] = buffer_load2(av, alane + 64 * t + (uint32_t)(2 * j + e) * 128, 0);
         }
-        anchor_store(av, buf, cn, half, 2 * kDepth, tid);
-        __syncthreads();
-        if (e0 < e1) {
-            const float2* arow = buf + row0 * 16 + (lane & 15);
+    };
+    auto load_spectrum = [&](PairLoads<R8>& d, int j) {
+        const uint32_t r = (uint32_t)min(2 * j, last);
+        d.x0 = buffer_load4(xv, xlane_e, r * (uint32_t)xstride);
+        d.x1 = buffer_load4(xv, xlane_e + 16, r * (uint32_t)xstride);
+    };
+    // component of the lane's phases: Re(a' D_b) with a' = a (rowtype == q), i a = (-Im a, Re a)
+    // for (Re row, Im part), -i a = (Im a, -Re a) for (Im row, Re part)
+    const bool rot = rowtype != q;
+    const uint32_t sx = (rowtype == 0 && q == 1) ? 0x80000000u : 0u;
+    const uint32_t sy = (rowtype == 1 && q == 0) ? 0x80000000u : 0u;
+
+    // this wave's element pairs j = e4 + 4 t, t < nt, in whole steps of kDepth pairs
+    const int npairs = (L + 1) >> 1;
+    const int nt = max(0, (npairs - e4 + 3) >> 2);
+    // steps of kDepth pairs, two per pass of the loop (a pass's waits count the loads of both its
+    // halves, not only its own half's)
+    const int steps = 2 * ((nt + 2 * kDepth - 1) / (2 * kDepth));
+    PairLoads<R8> buf[kDepth];
 #pragma unroll
-            for (int u = 0; u < kDepth; ++u) q[u].a = arow[u * 16];
-            const int steps = (e1 - e0 + kDepth - 1) / kDepth;
-            int e = e0;
-            for (int it = 0; it < steps; ++it, e += kDepth, arow += kDepth * 16) {
+    for (int u = 0; u < kDepth; ++u) {
+        load_phase(buf[u], e4 + 4 * u);
+        load_spectrum(buf[u], e4 + 4 * u);
+    }
+    // the loop is entered with these arrived (the compiler issues them in its own order; its
+    // waits in the loop then count only the loop's own loads)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    int j = e4;
+    for (int it = 0; it < steps; it += 2, j += 8 * kDepth) {
 #pragma unroll
-                for (int u = 0; u < kDepth; ++u) {
-                    // operands of element e + u from the buffer ...
-                    const ElemLoads& c = q[u];
+        for (int uu = 0; uu < 2 * kDepth; ++uu) {
+            const int u = uu % kDepth;
+            const PairLoads<R8>& c = buf[u];
+            // B operands of the 8 bins: (bin i, bin i + 4) from the lane's half runs
+            float bop[kBinBlock];
+            {
+                const float re[4] = {c.x0.x, c.x0.z, c.x1.x, c.x1.z};
+                const float im[4] = {c.x0.y, c.x0.w, c.x1.y, c.x1.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
                     const auto sw =
-                        __builtin_amdgcn_permlane32_swap(__float_as_uint(c.x.x), __float_as_uint(c.x.y), false, false);
-                    const float a0 = __builtin_fmaf(c.a.y, c.c.y, c.a.x * c.c.x);
-                    const float a1 = __builtin_fmaf(c.a.y, c.c.w, c.a.x * c.c.z);
-                    // ... then the buffer takes the element kDepth ahead (into the same registers;
-                    // the spectrum after the products that read its swapped copy)
-                    const int ln = min(e + u + kDepth, last);
-                    q[u].c = cload(ln);
-                    q[u].a = arow[(u + kDepth) * 16];
-                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, __uint_as_float(sw[0]), acc0, 0, 0, 0);
-                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, __uint_as_float(sw[1]), acc1, 0, 0, 0);
-                    __builtin_amdgcn_sched_barrier(0);  // the spectrum reload after both products
-                    q[u].x = xload(ln);
-                    // keeps each element's refill loads in its own step (the loads stay kDepth
-                    // steps ahead of their use instead of being moved next to it)
-                    __builtin_amdgcn_sched_barrier(0);
+                        __builtin_amdgcn_permlane16_swap(__float_as_uint(re[i]), __float_as_uint(im[i]), false, false);
+                    bop[i] = __uint_as_float(sw[0]);
+                    bop[i + 4] = __uint_as_float(sw[1]);
                 }
             }
+            // A operands: Re(a' D_b), D_b = D_1^b (b < 4), D_4 D_1^(b-4)
+            float aop[R8][kBinBlock];
+#pragma unroll
+            for (int t = 0; t < R8; ++t) {
+                const float2 a = c.a[t];
+                const float2 ap = rot ? make_float2(__uint_as_float(__float_as_uint(a.y) ^ sx),
+                                                    __uint_as_float(__float_as_uint(a.x) ^ sy))
+                                      : a;
+                const float2 d1 = make_float2(c.d[t].x, c.d[t].y), d4 = make_float2(c.d[t].z, c.d[t].w);
+                const float2 w1 = cmul2(ap, d1), w2 = cmul2(w1, d1);
+                const float2 w4 = cmul2(ap, d4), w5 = cmul2(w4, d1), w6 = cmul2(w5, d1);
+                aop[t][0] = ap.x;
+                aop[t][1] = w1.x;
+                aop[t][2] = w2.x;
+                aop[t][3] = w2.x * d1.x - w2.y * d1.y;
+                aop[t][4] = w4.x;
+                aop[t][5] = w5.x;
+                aop[t][6] = w6.x;
+                aop[t][7] = w6.x * d1.x - w6.y * d1.y;
+            }
+            // the buffer takes this wave's pair kDepth steps ahead (into the same registers: the
+            // phase operands now, the spectrum after the products that read its swapped copy)
+            __builtin_amdgcn_sched_barrier(0);
+            load_phase(buf[u], j + 4 * (uu + kDepth));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < R8; ++t)
+#pragma unroll
+                for (int b = 0; b < kBinBlock; ++b)
+                    acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[t][b], bop[b], acc[t][b], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            load_spectrum(buf[u], j + 4 * (uu + kDepth));
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
-    // the element halves: waves 4..7 hand their sums to waves 0..3 through LDS
-    __syncthreads();
-    float* red = reinterpret_cast<float*>(buf);
-    if (h == 1) {
+    // element quarters summed as (q0 + q2) + (q1 + q3): quarters 2, 3 (then 1) hand their sums
+    // to the wave below through slot 2 g + (e4 & 1) of LDS
+    constexpr int kSlot = R8 * kBinBlock * 4 * 64;  // floats per wave slot
+    auto put = [&](int slot) {
+        float* d = lds + slot * kSlot + lane;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            red[((p * 2 + 0) * 16 + v) * 64 + lane] = acc0[v];
-            red[((p * 2 + 1) * 16 + v) * 64 + lane] = acc1[v];
-        }
+        for (int t = 0; t < R8; ++t)
+#pragma unroll
+            for (int b = 0; b < kBinBlock; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) d[((t * kBinBlock + b) * 4 + v) * 64] = acc[t][b][v];
+    };
+    auto add = [&](int slot) {
+        const float* d = lds + slot * kSlot + lane;
+#pragma unroll
+        for (int t = 0; t < R8; ++t)
+#pragma unroll
+            for (int b = 0; b < kBinBlock; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[t][b][v] += d[((t * kBinBlock + b) * 4 + v) * 64];
+    };
+    if (e4 >= 2) put(2 * g + (e4 & 1));
+    __syncthreads();
+    if (e4 < 2) add(2 * g + e4);
+    __syncthreads();
+    if (e4 == 1) put(2 * g);
+    __syncthreads();
+    if (e4 == 0) add(2 * g);
+    __syncthreads();
+    // results to LDS as [column][angle][bin][Re, Im], then out as 64-byte runs (8 bins of one
+    // (i, o)), 8 threads per run
+    if (e4 == 0) {
+        const int col = 16 * g + (lane & 15);
+        const int comp = lane >> 5, o4 = ((lane >> 4) & 1) * 4;
+#pragma unroll
+        for (int t = 0; t < R8; ++t)
+#pragma unroll
+            for (int b = 0; b < kBinBlock; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    lds[col * kYColF + ((8 * t + o4 + v) * kBinBlock + b) * 2 + comp] = acc[t][b][v];
     }
     __syncthreads();
-    if (h == 0) {
+    const float2* yst = reinterpret_cast<const float2*>(lds);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            acc0[v] += red[((p * 2 + 0) * 16 + v) * 64 + lane];
-            acc1[v] += red[((p * 2 + 1) * 16 + v) * 64 + lane];
-        }
-    }
-    __syncthreads();
-    // results to LDS as runs [i][o][bin], then out as 64-byte runs, 8 threads per run
-    float2* yst = buf;
-    if (h == 0) {
-        const int col = lane & 31;
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            yst[col * kYCol + ol * kBinBlock + 2 * p] = make_float2(acc0[v], acc0[v + 8]);
-            yst[col * kYCol + ol * kBinBlock + 2 * p + 1] = make_float2(acc1[v], acc1[v + 8]);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 32 * 16 * kBinBlock / kContractThreads; ++u) {
         const int f = tid + u * kContractThreads;  // float2 f & 7 of run f >> 3
-        const int run = f >> 3, q = f & 7;
+        const int run = f >> 3, q8 = f & 7;
         const int il = run >> 4, ol = run & 15;
         const int i = ct * 32 + il, o = rt * 16 + ol;
-        if (i < ntx && o < M) Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q] = yst[il * kYCol + ol * kBinBlock + q];
+        if (ol < 8 * R8 && i < ntx && o < M)
+            Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q8] = yst[(il * kYColF) / 2 + ol * kBinBlock + q8];
     }
 }
 
@@ -297,7 +356,7 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
                                                     const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
                                                     int M, int L, int ncol, int kpad, float xscale, float yscale,
                                                     int kb, int rt, int ct) {
-    __shared__ __attribute__((aligned(16))) float2 buf[kBufFloat2];
+    __shared__ __attribute__((aligned(16))) float2 buf[kSplitBuf];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int p = wave & 3, h = wave >> 2;
@@ -319,11 +378,7 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
     for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
         const int cn = min(kAnchorChunk, L - c0);
         __syncthreads();
-        {
-            float4 av[kAnchorLoads];
-            anchor_load(av, ablk, c0, cn, tid);
-            anchor_store(av, buf, cn, cn, 0, tid);
-        }
+        stage_anchors(buf, ablk, c0, cn, tid);
         __syncthreads();
         const int half = (cn + 1) >> 1;
         const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
@@ -419,7 +474,7 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-        const int f = tid + u * kContractThreads;
+        const int f = tid + u * kSplitThreads;
         const int run = f >> 3, q = f & 7;
         const int il = run >> 4, ol = run & 15;
         const int i = ct * 32 + il, o = rt * 16 + ol;
@@ -427,16 +482,18 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
     }
 }
 
+template <int R8>
 __global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
-                                                                     const float4* __restrict__ cf,
+                                                                     const float4* __restrict__ d14,
                                                                      const float2* __restrict__ anc,
                                                                      float2* __restrict__ Y, int ntx, int M,
                                                                      int L, int ncol, int kpad) {
-    contract_body(X, cf, anc, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z);
+    __shared__ __attribute__((aligned(16))) float lds[contract_lds_floats<R8>()];
+    contract_body<R8>(X, d14, anc, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
 template <bool F16>
-__global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
+__global__ __launch_bounds__(kSplitThreads) void contract_split_kernel(
     const float2* __restrict__ X, const float4* __restrict__ cf, const float2* __restrict__ anc,
     float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad, float xscale, float yscale) {
     contract_split_body<F16>(X, cf, anc, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
@@ -447,18 +504,23 @@ __global__ __launch_bounds__(kContractThreads) void contract_split_kernel(
 // of frame entry blk[b], in the per-frame grid order (bin block fastest, then receive tile,
 // then transmit tile).  PREC: 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo.
 template <int PREC>
-__global__ __launch_bounds__(kContractThreads) void contract_grouped(const ContractEntry* __restrict__ tab,
-                                                                     const int32_t* __restrict__ blk,
-                                                                     float2* __restrict__ ws) {
+__global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads) void contract_grouped(
+    const ContractEntry* __restrict__ tab, const int32_t* __restrict__ blk, float2* __restrict__ ws) {
     const ContractEntry e = tab[blk[blockIdx.x]];
     int local = (int)blockIdx.x - e.block0;
     const int kb = local % e.nkb;
     local /= e.nkb;
     const int rt = local % e.nrt, ct = local / e.nrt;
     const PhaseTables pt{nullptr, e.M, reinterpret_cast<float4*>(ws + e.d_off)};
-    if constexpr (PREC == 0)
-        contract_body(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct);
-    else
+    if constexpr (PREC == 0) {
+        __shared__ __attribute__((aligned(16))) float lds[contract_lds_floats<2>()];
+        if (e.M <= 8)
+            contract_body<1>(ws + e.x_off, pt.d14(e.L), pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
+                             kb, rt, ct, lds);
+        else
+            contract_body<2>(ws + e.x_off, pt.d14(e.L), pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
+                             kb, rt, ct, lds);
+    } else
         contract_split_body<PREC == 2>(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
                                        e.xscale, e.yscale, kb, rt, ct);
 }
@@ -472,11 +534,17 @@ dim3 contract_grid(int log2n, int M, int ncol) { return dim3(contract_bin_blocks
 hipError_t launch_contract(int log2n, int precision, const float2* X, const PhaseTables& pt, float2* Y, int ntx,
                            int L, int ncol, int kpad, float xscale, hipStream_t st) {
     if (log2n < kMinLog2Fft || log2n > kMaxLog2Fft) return hipErrorInvalidValue;
-    const dim3 grid = contract_grid(log2n, pt.M, ncol), block(kContractThreads);
+    const dim3 grid = contract_grid(log2n, pt.M, ncol);
+    const dim3 block(precision == KK_PREC_FP32 ? kContractThreads : kSplitThreads);
     const float2* anc = pt.anc(L);
     switch (precision) {
         case KK_PREC_FP32:
-            hipLaunchKernelGGL(contract_kernel, grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L, ncol, kpad);
+            if (pt.M <= 8)
+                hipLaunchKernelGGL(contract_kernel<1>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L, ncol,
+                                   kpad);
+            else
+                hipLaunchKernelGGL(contract_kernel<2>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L, ncol,
+                                   kpad);
             break;
         case KK_PREC_BF16X3:
             hipLaunchKernelGGL((contract_split_kernel<false>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
@@ -495,11 +563,11 @@ hipError_t launch_contract_grouped(int log2n, int precision, const ContractEntry
                                    float2* ws, const int32_t* plan, hipStream_t st) {
     (void)plan;
     if (log2n < kMinLog2Fft || log2n > kMaxLog2Fft) return hipErrorInvalidValue;
-    const dim3 g(blocks), b(kContractThreads);
+    const dim3 g(blocks), b(kContractThreads), bs(kSplitThreads);
     switch (precision) {
         case KK_PREC_FP32: hipLaunchKernelGGL((contract_grouped<0>), g, b, 0, st, tab, blk, ws); break;
-        case KK_PREC_BF16X3: hipLaunchKernelGGL((contract_grouped<1>), g, b, 0, st, tab, blk, ws); break;
-        case KK_PREC_FP16X3: hipLaunchKernelGGL((contract_grouped<2>), g, b, 0, st, tab, blk, ws); break;
+        case KK_PREC_BF16X3: hipLaunchKernelGGL((contract_grouped<1>), g, bs, 0, st, tab, blk, ws); break;
+        case KK_PREC_FP16X3: hipLaunchKernelGGL((contract_grouped<2>), g, bs, 0, st, tab, blk, ws); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -246,12 +246,13 @@ __device__ __forceinline__ float2 exact_turn(int64_t k, int64_t s) {
 }
 
 // The contraction's phase tables (extra workgroups of a blocked forward launch; the layouts
-// are those of PhaseTables).  Work item e of table block b: a coefficient entry (rt, l, o % 16)
-// (D_1 .. D_7 of its angle and element, expanded into its four operand lanes for p = 0..3), or
+// are those of PhaseTables).  Work item e of table block b: a step entry (rt, l, o % 16) (D_1 ..
+// D_7 of its angle and element: its D14 entry, and its four Cf operand lanes for p = 0..3), or
 // four anchors W_{8 kb}[o][l] of consecutive angles.
 template <int LOG2N>
 __device__ __forceinline__ void phase_table_block(const int32_t* __restrict__ shift, int M, int L,
-                                                  float4* __restrict__ cf, float2* __restrict__ anc, int b) {
+                                                  float4* __restrict__ cf, float4* __restrict__ d14,
+                                                  float2* __restrict__ anc, int b) {
     constexpr int nkb = (1 << LOG2N) / 2 / kBinBlock;
     const int nrt = (M + 15) / 16;
     const int64_t e = (int64_t)b * fft_threads<LOG2N>() + threadIdx.x;
@@ -271,6 +272,7 @@ __device__ __forceinline__ void phase_table_block(const int32_t* __restrict__ sh
 #pragma unroll
             for (int j = 0; j < 8; ++j) d[j] = make_float2(0.f, 0.f);
         }
+        d14[((size_t)rt * L + l) * 16 + o16] = make_float4(d[1].x, d[1].y, d[4].x, d[4].y);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const float2 u = d[2 * p], v = d[2 * p + 1];
@@ -313,7 +315,7 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
                                                  const int32_t* __restrict__ shift, int M, float4* __restrict__ cf) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
-    __shared__ __attribute__((aligned(16))) float2 data[N + N / 16];
+    __shared__ __attribute__((aligned(16))) float2 data[N + N / 16 + 1];  // + the mirror slot of bin 0
     __shared__ float2 fac[64 + N / 64];
     const int tid = threadIdx.x;
     int t0, t1, i0 = 0, l0 = 0;
@@ -321,10 +323,14 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
     if constexpr (BLOCKED) {
         const int ntx = ntraces / L;
         const int npairs = (ntx + 1) / 2;
-        if (blk >= L * npairs) {  // uniform per workgroup, before any barrier
-            if (cf) phase_table_block<LOG2N>(shift, M, L, cf, PhaseTables{shift, M, cf}.anc(L), blk - L * npairs);
+        const int tb = cf ? (int)phase_table_blocks(M, L, LOG2N) : 0;
+        if (blk < tb) {  // uniform per workgroup, before any barrier
+            const PhaseTables pt{shift, M, cf};
+            phase_table_block<LOG2N>(shift, M, L, cf, pt.d14(L), pt.anc(L), blk);
             return;
         }
+        blk -= tb;
+        if (blk >= L * npairs) return;
         l0 = blk % L;
         i0 = 2 * (blk / L);
         t0 = i0 * L + l0;
@@ -366,6 +372,39 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
         middle_passes<LOG2N, 0, false>(data, fac, tid);
     pass_lds<LOG2N, F::radix(F::NPASS - 1), F::ns(F::NPASS - 1), false>(data, fac, tid);
     // unpack the two real spectra with the analytic mask, two bins per thread and record
+    if constexpr (BLOCKED) {
+        // bins 2kp, 2kp+1 < n/2 of transmits i0 and i0+1 (zeros for a missing partner): the four
+        // threads of one bin block write one 128-byte line (64 bytes per record); bin 0 takes
+        // Z[0] alone (the slot read as its mirror Z[n] is the spare one after the data)
+        constexpr int TH = fft_threads<LOG2N>();
+        constexpr int ITER = (N / 4 + TH - 1) / TH;
+        float4* o = reinterpret_cast<float4*>(out + spec_index(2 * tid, l0, i0, L, ncol));
+        const size_t ostep = (size_t)(TH / 4) * L * ncol * 4;  // float4s between iterations
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const int k = 2 * (tid + it * TH);
+            if ((N / 4) % TH != 0 && k >= N / 2) break;
+            const float2 z0 = data[pad(k)], z1 = data[pad(k + 1)];
+            const float2 m0 = data[pad(N - k)], m1 = data[pad(N - k - 1)];
+            float4 A = make_float4(z0.x + m0.x, z0.y - m0.y, z1.x + m1.x, z1.y - m1.y);
+            float4 B = make_float4(z0.y + m0.y, m0.x - z0.x, z1.y + m1.y, m1.x - z1.x);
+            if (it == 0 && tid == 0) {
+                A.x = z0.x;
+                A.y = 0.f;
+                B.x = z0.y;
+                B.y = 0.f;
+            }
+            o[it * ostep] = A;
+            o[it * ostep + kBinBlock / 2] = B;
+        }
+        if (tid == 0) {  // bin n/2 (read by the inverse transform's Nyquist sum), then a zero bin
+            const float2 z = data[pad(N / 2)];
+            float4* q = reinterpret_cast<float4*>(out + spec_index(N / 2, l0, i0, L, ncol));
+            q[0] = make_float4(z.x, 0.f, 0.f, 0.f);
+            q[kBinBlock / 2] = make_float4(z.y, 0.f, 0.f, 0.f);
+        }
+        return;
+    }
     for (int kp = tid; 2 * kp < kpad; kp += fft_threads<LOG2N>()) {
         float2 A[2], B[2];
 #pragma unroll
@@ -384,19 +423,11 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
                 }
             }
         }
-        if constexpr (BLOCKED) {
-            // bins 2kp, 2kp+1 of transmits i0 and i0+1 (zeros for a missing partner): the four
-            // threads of one bin block write one 128-byte line (64 bytes per record)
-            float4* o = reinterpret_cast<float4*>(out + spec_index(2 * kp, l0, i0, L, ncol));
-            o[0] = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
-            o[kBinBlock / 2] = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
-        } else {
-            // four neighbouring threads complete one 64-byte run of 8 bins per record
-            float2* o0 = out + (size_t)t0 * kpad;
-            float2* o1 = out + (size_t)t1 * kpad;
-            *reinterpret_cast<float4*>(o0 + 2 * kp) = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
-            if (has1) *reinterpret_cast<float4*>(o1 + 2 * kp) = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
-        }
+        // trace layout: four neighbouring threads complete one 64-byte run of 8 bins per record
+        float2* o0 = out + (size_t)t0 * kpad;
+        float2* o1 = out + (size_t)t1 * kpad;
+        *reinterpret_cast<float4*>(o0 + 2 * kp) = make_float4(A[0].x, A[0].y, A[1].x, A[1].y);
+        if (has1) *reinterpret_cast<float4*>(o1 + 2 * kp) = make_float4(B[0].x, B[0].y, B[1].x, B[1].y);
     }
 }
 

@@ -20,14 +20,15 @@ __host__ __device__ inline size_t spec_index(int k, int l, int i, int L, int nco
 }
 
 // Phase tables of the contraction, written by the extra workgroups of a blocked forward launch
-// (nrt = receive tiles of 16 angles, nkb = n / 16 bin blocks; rows o >= M are zero):
-//   coefficients Cf[((rt 4 + p) L + l) 64 + lane] (float4), for lane = the lane of the FP32
-//     contraction's MFMA operand A: row r = lane % 32 (Re rows r < 16, Im rows r >= 16, angle
-//     o = 16 rt + r % 16) and element part q = lane / 32; (x, y) for bin offset j = 2p and (z, w)
-//     for j = 2p + 1 are chosen so that the operand is Re(a) x + Im(a) y for the bin block's
-//     anchor a: (Re D_j, -Im D_j) for (Re row, Re part) and (Im row, Im part), (Im D_j, Re D_j) for
-//     (Im row, Re part), (-Im D_j, -Re D_j) for (Re row, Im part), where
-//     D_j[o][l] = exp(2 pi i ((j shift[o][l]) mod (n 2^22)) / (n 2^22));
+// (nrt = receive tiles of 16 angles, nkb = n / 16 bin blocks; rows o >= M are zero), with
+// D_j[o][l] = exp(2 pi i ((j shift[o][l]) mod (n 2^22)) / (n 2^22)) the phase step of j bins:
+//   coefficients Cf[((rt 4 + p) L + l) 64 + lane] (float4), for lane = the lane of the
+//     split-precision contraction's operand A: row r = lane % 32 (Re rows r < 16, Im rows
+//     r >= 16, angle o = 16 rt + r % 16) and element part q = lane / 32; (x, y) for j = 2p and
+//     (z, w) for j = 2p + 1 are chosen so that the operand is Re(a) x + Im(a) y for the bin
+//     block's anchor a: (Re D_j, -Im D_j) for (Re row, Re part) and (Im row, Im part),
+//     (Im D_j, Re D_j) for (Im row, Re part), (-Im D_j, -Re D_j) for (Re row, Im part);
+//   steps D14[(rt L + l) 16 + o % 16] (float4) = (D_1, D_4)[o][l];
 //   anchors Anc[((kb nrt + rt) L + l) 16 + o % 16] (float2) = W_{8 kb}[o][l], the Eq. 3 phase of
 //     the first bin of block kb.
 // The anchor times the step of the bin's offset in its block gives the bin's phase.
@@ -35,33 +36,37 @@ __host__ __device__ inline int contract_bin_blocks(int log2n) { return (1 << log
 __host__ __device__ inline size_t phase_cf_floats4(int M, int L) {
     return (size_t)((M + 15) / 16) * 4 * (size_t)L * 64;
 }
+__host__ __device__ inline size_t phase_d14_floats4(int M, int L) { return (size_t)((M + 15) / 16) * (size_t)L * 16; }
 __host__ __device__ inline size_t phase_anc_floats2(int M, int L, int log2n) {
     return (size_t)contract_bin_blocks(log2n) * ((M + 15) / 16) * (size_t)L * 16;
 }
 inline size_t phase_table_bytes(int M, int L, int log2n) {
-    return phase_cf_floats4(M, L) * 16 + phase_anc_floats2(M, L, log2n) * 8;
+    return (phase_cf_floats4(M, L) + phase_d14_floats4(M, L)) * 16 + phase_anc_floats2(M, L, log2n) * 8;
 }
 
 // Threads per workgroup of the FFT kernels for a transform of 2^log2n points.
-constexpr int fft_threads_for(int log2n) { return log2n >= 13 ? 512 : 256; }
-// Work items of the phase tables: one per (rt, l, o % 16) coefficient entry (its four lanes, all
-// p), then one per four anchors (kb, rt, l, o % 16 / 4).
-inline int64_t phase_table_items(int M, int L, int log2n) {
+__host__ __device__ constexpr int fft_threads_for(int log2n) { return log2n >= 13 ? 512 : 256; }
+// Work items of the phase tables: one per (rt, l, o % 16) step entry (its Cf lanes for all p and
+// its D14 entry), then one per four anchors (kb, rt, l, o % 16 / 4).
+__host__ __device__ inline int64_t phase_table_items(int M, int L, int log2n) {
     const int64_t nrt = (M + 15) / 16;
     return nrt * L * 16 + (int64_t)contract_bin_blocks(log2n) * nrt * L * 4;
 }
-// Workgroups of a blocked forward launch that write the phase tables (after the record pairs).
-inline int64_t phase_table_blocks(int M, int L, int log2n) {
+// Workgroups of a blocked forward launch that write the phase tables (before the record pairs).
+__host__ __device__ inline int64_t phase_table_blocks(int M, int L, int log2n) {
     const int64_t t = fft_threads_for(log2n);
     return (phase_table_items(M, L, log2n) + t - 1) / t;
 }
 
-// Where a blocked forward launch writes the phase tables: Cf at base, Anc right after it.
+// Where a blocked forward launch writes the phase tables: Cf at base, then D14, then Anc.
 struct PhaseTables {
     const int32_t* shift;  // [M][L] Q.22 advances
     int M;
-    float4* cf;            // phase_cf_floats4(M, L) entries, then phase_anc_floats2(M, L, log2n) anchors
-    __host__ __device__ float2* anc(int L) const { return reinterpret_cast<float2*>(cf + phase_cf_floats4(M, L)); }
+    float4* cf;            // phase_cf_floats4(M, L) entries
+    __host__ __device__ float4* d14(int L) const { return cf + phase_cf_floats4(M, L); }
+    __host__ __device__ float2* anc(int L) const {
+        return reinterpret_cast<float2*>(cf + phase_cf_floats4(M, L) + phase_d14_floats4(M, L));
+    }
 };
 
 constexpr int kMinLog2Fft = 8;
@@ -79,8 +84,9 @@ inline int log2_exact(int64_t n) {
 // and imaginary parts of one complex FFT.  Output bins k = 0..kpad-1 (zero above n/2):
 //   blocked: out[spec_index(k, l, i, L, ncol)] for record t = i L + l (contraction layout;
 //            records i and i+1 of element l share a workgroup, a missing partner record of
-//            an odd transmit count is written as zeros); the launch also writes the phase
-//            tables *ph of the contraction (extra workgroups), when ph is given
+//            an odd transmit count is written as zeros; of the last block only bin n/2 is
+//            written); the launch also writes the phase tables *ph of the contraction (extra
+//            workgroups, ahead of the record pairs), when ph is given
 //   else:    out[t * kpad + k]                                   (trace layout)
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
                               int ncol, int kpad, hipStream_t st, const PhaseTables* ph = nullptr);
