@@ -42,6 +42,8 @@ EXPORTS = [
     "kk_net_prepare", "kk_net_forward", "kk_net_backward", "kk_net_adam", "kk_net_train_step", "kk_net_merge",
     "kk_clear", "kk_beamform_static", "kk_beamform_static_max_bytes",
 ]
+# plan header words (the PlanWord order of the library's plan format): window class, pair shares
+PLAN_WORD_CAP, PLAN_WORD_SPLIT = 13, 24
 NET_LAYERS, NET_WIDTH, NET_IN = 6, 32, 8
 NET_PARAMS, NET_GRADS, NET_MOMENT1, NET_MOMENT2 = 0, 1, 2, 3
 
