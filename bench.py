@@ -670,12 +670,22 @@ def main():
     inten = torch.empty((w.X, w.Z), dtype=torch.float32, device=dev)
     bws = torch.zeros(max(1, kk.beamform_workspace_bytes(su.plan)), dtype=torch.uint8, device=dev)
 
+    # the phase tables of the decomposition depend on the geometry only (like the plan): written
+    # once per workspace by kk_decompose_prepare, outside the timed frames
+    kk.decompose_prepare(su.geom, w.N, shift, su.M, su.tpad, ws)
+
     def frame():
-        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
+        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws, prepared=True)
         kk.beamform(rt, su.plan, plan_dev, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT, ws=bws)
 
     def decompose_only():
+        kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws, prepared=True)
+
+    def decompose_unprepared():
         kk.decompose(rf, su.geom, shift, su.M, su.tpad, out=rt, ws=ws)
+
+    def prepare_only():
+        kk.decompose_prepare(su.geom, w.N, shift, su.M, su.tpad, ws)
 
     def gather_only():
         kk.beamform(rt, su.plan, plan_dev, image=img, intensity=inten, mode=kk.COMPOUND_INCOHERENT, ws=bws)
@@ -697,10 +707,11 @@ def main():
     for k in range(1, nstreams):
         b = {key: torch.empty_like(v) for key, v in bufs[0].items() if key != "rf"}
         b["rf"] = torch.roll(rf, shifts=97 * k, dims=2).contiguous()
+        kk.decompose_prepare(su.geom, w.N, shift, su.M, su.tpad, b["ws"])
         bufs.append(b)
 
     def frame_on(b, st):
-        kk.decompose(b["rf"], su.geom, shift, su.M, su.tpad, out=b["rt"], ws=b["ws"], stream=st)
+        kk.decompose(b["rf"], su.geom, shift, su.M, su.tpad, out=b["rt"], ws=b["ws"], stream=st, prepared=True)
         kk.beamform(b["rt"], su.plan, plan_dev, image=b["img"], intensity=b["inten"], mode=kk.COMPOUND_INCOHERENT,
                     ws=b["bws"], stream=st)
 
@@ -737,7 +748,10 @@ def main():
     for b in bufs:
         chk = dict(rf=b["rf"], rt=torch.empty_like(rt), ws=torch.empty_like(ws), img=torch.empty_like(img),
                    inten=torch.empty_like(inten), bws=torch.zeros_like(bws))
-        frame_on(chk, cur)
+        # the check frame takes the unprepared entry point (tables written in the call)
+        kk.decompose(chk["rf"], su.geom, shift, su.M, su.tpad, out=chk["rt"], ws=chk["ws"], stream=cur)
+        kk.beamform(chk["rt"], su.plan, plan_dev, image=chk["img"], intensity=chk["inten"],
+                    mode=kk.COMPOUND_INCOHERENT, ws=chk["bws"], stream=cur)
         torch.cuda.synchronize()
         streams_ok &= bool(torch.equal(chk["img"], b["img"])) and bool(torch.equal(chk["inten"], b["inten"]))
     # one frame at a time on one stream (frame latency)
@@ -748,6 +762,9 @@ def main():
     log("graph replay %s" % json.dumps(graph_rep))
 
     ms_dec = timed(decompose_only, args.steps, 5, torch, repeats=3)
+    ms_dec_unprepared = timed(decompose_unprepared, args.steps, 5, torch, repeats=3)
+    ms_prepare = timed(prepare_only, max(10, args.steps // 4), 3, torch, repeats=2)
+    kk.decompose_prepare(su.geom, w.N, shift, su.M, su.tpad, ws)
     ms_gather = timed(gather_only, args.steps, 5, torch, repeats=3)
     ms_gather_kernel = timed(gather_kernel_only, args.steps, 5, torch, repeats=3)
     res = {}
@@ -862,7 +879,10 @@ def main():
         "frames_per_s": round(1e3 / ms, 1),
         "streams": nstreams,
         "streams_match_single_frames": streams_ok,
-        "stages_us": {"decompose": round(ms_dec * 1e3, 2), "gather": round(ms_gather * 1e3, 2),
+        "stages_us": {"decompose": round(ms_dec * 1e3, 2),
+                      "decompose_writing_phase_tables": round(ms_dec_unprepared * 1e3, 2),
+                      "phase_tables_per_geometry": round(ms_prepare * 1e3, 2),
+                      "gather": round(ms_gather * 1e3, 2),
                       "gather_kernel": round(ms_gather_kernel * 1e3, 2),
                       "frame": round(ms * 1e3, 2), "frame_one_stream": round(ms_single * 1e3, 2)},
         "beamform_gpixpair_per_s": round(gather_rate / 1e9, 1),

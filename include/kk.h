@@ -202,6 +202,24 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
                      int32_t M, int32_t tpad, int32_t precision, float* rf_theta,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* kk_decompose_prepare (device) - the geometry-dependent part of kk_decompose (Eq. 3, Sec.
+ * II-F): the contraction's phase tables, the phase of the first bin of every 8-bin block and the
+ * steps to the other bins (each from an exact integer turn count of shift_q, evaluated in FP64
+ * and rounded once), written into ws.  They depend only on g, N, M, tpad and the contents of
+ * shift_q, like a beamforming plan: a workspace prepared once serves any number of
+ * kk_decompose_prepared calls with those same arguments.
+ * Errors: as kk_decompose.
+ * kk_decompose_prepared (device) - kk_decompose on a workspace that kk_decompose_prepare has
+ * prepared for the same g, N, M, tpad and shift table (the caller guarantees it; other inputs
+ * give wrong results, not errors): the same arguments and results, bit for bit, without
+ * rewriting the tables.  kk_decompose writes them in every call and may use any workspace. */
+int32_t kk_decompose_prepare(const kk_geom* g, int32_t N, const int32_t* shift_q, int32_t M,
+                             int32_t tpad, int32_t precision, void* ws, size_t ws_bytes,
+                             void* stream);
+int32_t kk_decompose_prepared(const int16_t* rf, int32_t N, const kk_geom* g,
+                              const int32_t* shift_q, int32_t M, int32_t tpad, int32_t precision,
+                              float* rf_theta, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * kk_beamform (device) - Eq. 5 per set:
  *   image[s][k][m] = sum_{p in set s} v_p,  q = A[p][k] + B[p][m] (Q16.16 samples),

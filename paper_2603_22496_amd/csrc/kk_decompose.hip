@@ -616,12 +616,15 @@ bool decompose_layout(const kk_geom* g, int32_t N, int32_t M, int32_t tpad, Deco
     return true;
 }
 
-// Forward transform (with the phase tables) and the per-bin contraction of one frame into Y.
+// Forward transform (with the phase tables unless the workspace holds them already) and the
+// per-bin contraction of one frame into Y.
 hipError_t decompose_front(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M,
-                           int32_t precision, const DecomposeLayout& d, unsigned char* w, float2* Y, hipStream_t st) {
+                           int32_t precision, const DecomposeLayout& d, unsigned char* w, float2* Y, hipStream_t st,
+                           bool tables_ready = false) {
     float2* X = reinterpret_cast<float2*>(w + d.x_off);
     const PhaseTables pt{shift_q, M, reinterpret_cast<float4*>(w + d.d_off)};
-    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st, &pt);
+    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st,
+                                      tables_ready ? nullptr : &pt);
     if (e != hipSuccess) return e;
     const float xscale = precision == KK_PREC_FP16X3 ? std::ldexp(1.0f, fp16_prescale_exponent(g->T)) : 1.0f;
     return launch_contract(d.log2n, precision, X, pt, Y, N, g->L, d.ncol, d.kpad, xscale, st);
@@ -659,8 +662,11 @@ size_t kk_decompose_workspace_bytes(const kk_geom* g, int32_t N, int32_t M, int3
     return d.total;
 }
 
-int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M, int32_t tpad,
-                     int32_t precision, float* rf_theta, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+// kk_decompose and kk_decompose_prepared (tables_ready: the workspace holds the phase tables).
+int32_t decompose_call(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M, int32_t tpad,
+                       int32_t precision, float* rf_theta, void* ws, size_t ws_bytes, void* stream,
+                       bool tables_ready) {
     using namespace kk;
     if (!rf || !g || !shift_q || !rf_theta || !ws) return KK_E_NULL;
     if (precision != KK_PREC_FP32 && precision != KK_PREC_BF16X3 && precision != KK_PREC_FP16X3)
@@ -673,12 +679,44 @@ int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32
     hipStream_t st = (hipStream_t)stream;
     unsigned char* w = static_cast<unsigned char*>(ws);
     float2* Y = reinterpret_cast<float2*>(w + d.y_off);
-    if (decompose_front(rf, N, g, shift_q, M, precision, d, w, Y, st) != hipSuccess) return KK_E_HIP;
+    if (decompose_front(rf, N, g, shift_q, M, precision, d, w, Y, st, tables_ready) != hipSuccess) return KK_E_HIP;
     NyquistSum nyq{reinterpret_cast<const float2*>(w + d.x_off), shift_q, M, g->L, d.ncol};
     if (launch_fft_inverse(Y, N * M, d.kpad, d.log2n, reinterpret_cast<float2*>(rf_theta), g->T, st, &nyq) !=
         hipSuccess)
         return KK_E_HIP;
     return KK_OK;
+}
+}  // namespace
+
+int32_t kk_decompose(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M, int32_t tpad,
+                     int32_t precision, float* rf_theta, void* ws, size_t ws_bytes, void* stream) {
+    return decompose_call(rf, N, g, shift_q, M, tpad, precision, rf_theta, ws, ws_bytes, stream, false);
+}
+
+int32_t kk_decompose_prepare(const kk_geom* g, int32_t N, const int32_t* shift_q, int32_t M, int32_t tpad,
+                             int32_t precision, void* ws, size_t ws_bytes, void* stream) {
+    using namespace kk;
+    if (!g || !shift_q || !ws) return KK_E_NULL;
+    if (precision != KK_PREC_FP32 && precision != KK_PREC_BF16X3 && precision != KK_PREC_FP16X3)
+        return KK_E_UNSUPPORTED;
+    if (N < 1 || M < 1 || g->L < 1 || g->L > 65536 || g->T < 1) return KK_E_ARG;
+    DecomposeLayout d;
+    if (!decompose_layout(g, N, M, tpad, &d)) return KK_E_ARG;
+    if ((int64_t)N * g->L > 0x7fffffff || (int64_t)N * M > 0x7fffffff) return KK_E_ARG;
+    if (ws_bytes < d.total) return KK_E_WORKSPACE;
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    const PhaseTables pt{shift_q, M, reinterpret_cast<float4*>(w + d.d_off)};
+    // a blocked forward launch over no records: only its phase-table workgroups
+    return launch_fft_forward(nullptr, 0, g->T, d.log2n, reinterpret_cast<float2*>(w + d.x_off), true, g->L, d.ncol,
+                              d.kpad, (hipStream_t)stream, &pt) == hipSuccess
+               ? KK_OK
+               : KK_E_HIP;
+}
+
+int32_t kk_decompose_prepared(const int16_t* rf, int32_t N, const kk_geom* g, const int32_t* shift_q, int32_t M,
+                              int32_t tpad, int32_t precision, float* rf_theta, void* ws, size_t ws_bytes,
+                              void* stream) {
+    return decompose_call(rf, N, g, shift_q, M, tpad, precision, rf_theta, ws, ws_bytes, stream, true);
 }
 
 int32_t kk_spectrum_bins(int32_t tpad) {

@@ -32,7 +32,8 @@ WINDOW_CLASSES = (64, 128, 192, 256, 320, 384, 448, 512)
 
 EXPORTS = [
     "kk_select_pairs", "kk_build_luts", "kk_build_das_rx", "kk_beamform_plan",
-    "kk_decompose_workspace_bytes", "kk_decompose", "kk_beamform_workspace_bytes", "kk_beamform",
+    "kk_decompose_workspace_bytes", "kk_decompose", "kk_decompose_prepare", "kk_decompose_prepared",
+    "kk_beamform_workspace_bytes", "kk_beamform",
     "kk_compound", "das_plan", "das_workspace_bytes", "das_beamform", "kk_status_string",
     "kk_ensemble_default_tuning", "kk_ensemble_plan", "kk_ensemble_query", "kk_ensemble_frame_query",
     "kk_ensemble_run", "kk_ensemble_graph_create", "kk_ensemble_graph_launch", "kk_ensemble_graph_destroy",
@@ -120,6 +121,8 @@ def lib():
             "kk_beamform_plan": [_i32p, _i32, _i32, _i32, _i32, _i32, _i32p, _i32p, _i32p, _i32p, _i32,
                                  ctypes.POINTER(Grid), _vp, _sz, _szp],
             "kk_decompose": [_vp, _i32, ctypes.POINTER(Geom), _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp],
+            "kk_decompose_prepare": [ctypes.POINTER(Geom), _i32, _vp, _i32, _i32, _i32, _vp, _sz, _vp],
+            "kk_decompose_prepared": [_vp, _i32, ctypes.POINTER(Geom), _vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp],
             "kk_beamform": [_vp, _i32, _i32, _i32, _vp, _vp, _sz, _vp, _vp, _i32, _vp, _sz, _vp],
             "kk_compound": [_vp, _i32, _i32, _i32, _i32, _vp, _vp],
             "das_plan": [_i32, ctypes.POINTER(Geom), _i32p, _i32p, _i32p, _i32, ctypes.POINTER(Grid), _vp, _sz,
@@ -313,8 +316,9 @@ def decompose_workspace_bytes(g: Geom, N: int, M: int, tpad: int, precision: int
 
 
 def decompose(rf, g: Geom, shift_q, M: int, tpad: int, out=None, ws=None, precision: int = PREC_FP32,
-              stream=None):
-    """rf int16 [N][L][T] and shift_q int32 [M][L] on the device -> complex64 [N][M][T]."""
+              stream=None, prepared: bool = False):
+    """rf int16 [N][L][T] and shift_q int32 [M][L] on the device -> complex64 [N][M][T].
+    prepared: ws was prepared by decompose_prepare for this geometry (kk_decompose_prepared)."""
     N = rf.shape[0]
     new = []
     if out is None:
@@ -322,13 +326,24 @@ def decompose(rf, g: Geom, shift_q, M: int, tpad: int, out=None, ws=None, precis
         new.append(out)
     nbytes = decompose_workspace_bytes(g, N, M, tpad, precision)
     if ws is None:
+        if prepared:
+            raise ValueError("a prepared decomposition needs its prepared workspace")
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=rf.device)
         new.append(ws)
-    st = lib().kk_decompose(_dev(rf), N, ctypes.byref(g), _dev(shift_q), M, tpad, precision, _dev(out),
-                            _dev(ws), ws.numel() * ws.element_size(), _stream(stream))
+    name = "kk_decompose_prepared" if prepared else "kk_decompose"
+    st = getattr(lib(), name)(_dev(rf), N, ctypes.byref(g), _dev(shift_q), M, tpad, precision, _dev(out),
+                              _dev(ws), ws.numel() * ws.element_size(), _stream(stream))
     _bind(stream, *new)
-    _check("kk_decompose", st)
+    _check(name, st)
     return out
+
+
+def decompose_prepare(g: Geom, N: int, shift_q, M: int, tpad: int, ws, precision: int = PREC_FP32, stream=None):
+    """Writes the phase tables of (g, N, shift_q, M, tpad) into ws (kk_decompose_prepare)."""
+    st = lib().kk_decompose_prepare(ctypes.byref(g), N, _dev(shift_q), M, tpad, precision, _dev(ws),
+                                    ws.numel() * ws.element_size(), _stream(stream))
+    _check("kk_decompose_prepare", st)
+    return ws
 
 
 def beamform_workspace_bytes(plan_host: np.ndarray) -> int:

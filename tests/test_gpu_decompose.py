@@ -74,6 +74,31 @@ def test_shapes_and_random_shifts(kk, N, L, T, M, tpad, seed):
         assert _rel(got[:, o], ref[:, o]) <= 3 * TOL
 
 
+@pytest.mark.parametrize("N,L,T,M,tpad,precision", [
+    (31, 128, 2048, 13, 4096, 0),   # vernier shape
+    (5, 7, 333, 17, 512, 0),        # odd element count, two receive tiles
+    (3, 9, 1000, 5, 1024, 1),       # BF16 hi+lo
+    (4, 6, 700, 3, 1024, 2),        # FP16 hi+lo
+])
+def test_prepared_workspace_equals_unprepared_bit_for_bit(kk, N, L, T, M, tpad, precision):
+    """kk_decompose_prepare once, then kk_decompose_prepared on two different records, each bit for
+    bit equal to kk_decompose (which rewrites the tables every call)."""
+    import torch
+    rng = np.random.default_rng(N * 1000 + L)
+    shift = rng.integers(-2 ** 31, 2 ** 31 - 1, size=(M, L)).astype(np.int32)
+    g = kk.geom(L, T, 0.3e-3, 1540.0, 20e6, 0.0)
+    sh = kk.to_device(shift)
+    nbytes = kk.decompose_workspace_bytes(g, N, M, tpad, precision)
+    ws = torch.full((nbytes,), 0xAB, dtype=torch.uint8, device="cuda")
+    kk.decompose_prepare(g, N, sh, M, tpad, ws, precision=precision)
+    for k in range(2):
+        rf = kk.to_device(rng.integers(-32768, 32767, size=(N, L, T)).astype(np.int16))
+        got = kk.decompose(rf, g, sh, M, tpad, ws=ws, precision=precision, prepared=True)
+        ref = kk.decompose(rf, g, sh, M, tpad, precision=precision)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), (k, float((got - ref).abs().max()))
+
+
 def test_vernier_rf_theta(kk):
     w = C.VERNIER
     ds = C.speckle_dataset(w, seed=2, n_scat=20000)
