@@ -475,51 +475,62 @@ __device__ __forceinline__ void fft_inverse_body(const float2* __restrict__ in, 
     constexpr int K = N / 2 + 1;
     __shared__ float2 data[N + N / 16];
     __shared__ float2 fac[64 + N / 64];
+    __shared__ float2 wsum[fft_threads<LOG2N>() / 64];
     const int tid = threadIdx.x;
-    make_factors<LOG2N>(fac, tid);
     const float2* y = in + (size_t)t * kpad;
-    float2 ynyq = make_float2(0.f, 0.f);
+    // first pass inputs, the K non-negative bins (negative bins are zero), loaded first so that
+    // the Nyquist sum's loads and the factor tables overlap them
+    constexpr int R = F::radix(0);
+    constexpr int NB = N / R;
+    constexpr int PER = (NB + fft_threads<LOG2N>() - 1) / fft_threads<LOG2N>();
+    float2 v[PER][R];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int bb = tid + p * fft_threads<LOG2N>();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = bb + r * NB;
+            v[p][r] = (bb < NB && 2 * r <= R && k < K && !(NYQ && k == N / 2)) ? y[k] : make_float2(0.f, 0.f);
+        }
+    }
+    float2 part = make_float2(0.f, 0.f);
     if constexpr (NYQ) {
         // Eq. 3 at k = n/2: the advance s gives exp(i pi (s mod 2^23) / 2^22)
         const int i = t / nyq.M, o = t - (t / nyq.M) * nyq.M;
-        float2 part = make_float2(0.f, 0.f);
         for (int l = tid; l < nyq.L; l += fft_threads<LOG2N>()) {
             const uint32_t s = (uint32_t)nyq.shift[(size_t)o * nyq.L + l];
+            const float2 x = nyq.X[spec_index(N / 2, l, i, nyq.L, nyq.ncol)];
             float sn, cs;
             sincospif((float)(s & 0x7FFFFFu) * (1.0f / 4194304.0f), &sn, &cs);
-            const float2 x = nyq.X[spec_index(N / 2, l, i, nyq.L, nyq.ncol)];
             part.x += cs * x.x - sn * x.y;
             part.y += cs * x.y + sn * x.x;
         }
-        data[tid] = part;
-        __syncthreads();
-        for (int h = fft_threads<LOG2N>() / 2; h > 0; h >>= 1) {
-            if (tid < h) data[tid] = cadd(data[tid], data[tid + h]);
-            __syncthreads();
-        }
-        ynyq = data[0];
-        __syncthreads();
     }
-    {  // first pass from the K non-negative bins (negative bins are zero)
-        constexpr int R = F::radix(0);
-        constexpr int NB = N / R;
-        constexpr int PER = (NB + fft_threads<LOG2N>() - 1) / fft_threads<LOG2N>();
+    make_factors<LOG2N>(fac, tid);
+    if constexpr (NYQ) {
+        // the sum over elements: within each wave by lane exchanges, then over the waves
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            part.x += __shfl_xor(part.x, m);
+            part.y += __shfl_xor(part.y, m);
+        }
+        if ((tid & 63) == 0) wsum[tid >> 6] = part;
+        __syncthreads();
+        if (tid == 0) {  // bin n/2 enters butterfly 0 as its input R/2
+            float2 ynyq = wsum[0];
+#pragma unroll
+            for (int w = 1; w < fft_threads<LOG2N>() / 64; ++w) ynyq = cadd(ynyq, wsum[w]);
+            v[0][R / 2] = ynyq;
+        }
+    }
+    {  // first pass
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int bb = tid + p * fft_threads<LOG2N>();
             if (bb < NB) {
-                float2 v[R];
+                Dft<R, true>::run(v[p]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int k = bb + r * NB;
-                    if (2 * r > R)  // k > n/2: the negative bins are zero
-                        v[r] = make_float2(0.f, 0.f);
-                    else
-                        v[r] = (NYQ && k == N / 2) ? ynyq : (k < K ? y[k] : make_float2(0.f, 0.f));
-                }
-                Dft<R, true>::run(v);
-#pragma unroll
-                for (int r = 0; r < R; ++r) data[write_base<N, R, 1>(bb) + r * write_step<N, R, 1>()] = v[r];
+                for (int r = 0; r < R; ++r) data[write_base<N, R, 1>(bb) + r * write_step<N, R, 1>()] = v[p][r];
             }
         }
         __syncthreads();
