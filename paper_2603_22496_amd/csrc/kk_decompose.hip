@@ -5,12 +5,14 @@
 //      same launch writes the phase tables of step 2 (PhaseTables);
 //   2. per bin k the complex contraction Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] with
 //      W_k[o][l] = exp(2 pi i r / (n 2^22)), r = (k shift[o][l]) mod (n 2^22), on MFMA
-//      (v_mfma_f32_32x32x2_f32: one complex element l per instruction, 16 receive angles x
-//      {Re, Im} rows by 32 transmit columns; 8 bins per workgroup, a bin pair per wave);
+//      (FP32: v_mfma_f32_16x16x4_f32, two complex elements per instruction, 8 receive angles x
+//      {Re, Im} rows by 16 transmit columns, up to 32 angles and 8 bins per workgroup; split
+//      precision: v_mfma_f32_32x32x16_{bf16,f16} on hi + lo halves);
 //   3. inverse FFT of each (i, o) spectrum, first T samples.
-// Every phase comes from an exact integer turn count evaluated in FP64 and rounded once: the
-// anchor W_{8 kb} of each bin block and the steps D_j (j = 0..7) within a block, so that
-// W_{8 kb + j} = W_{8 kb} D_j is one complex product (two roundings) away from exact.
+// Every table phase comes from an exact integer turn count evaluated in FP64 and rounded once:
+// the anchor W_{8 kb} of each bin block and the in-block steps, W_{8 kb + j} = W_{8 kb} D_j.
+// The split-precision path reads D_j itself (one complex product from the anchor); the FP32
+// path reads D_1 and D_4 and forms D_j = D_1^j or D_4 D_1^(j-4) (at most three products).
 // Also the DAS comparator entry point (analytic channel data + delay-gather).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,18 +28,20 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// FP32 contraction workgroup: one block of 8 bins, R8 tiles of 8 receive angles (R8 = 1 when
-// M <= 8, else 2: 16 angles), 32 transmit columns; wave w takes column group g = w % 2 (16
-// transmits) and element quarter e4 = w / 2 (element pairs 2j, 2j+1 with j = e4 (mod 4)), all 8
-// bins; the quarters are summed at the end in a fixed order.
-constexpr int kContractWaves = 8;
+// FP32 contraction workgroup: one block of 8 bins, R8 tiles of 8 receive angles
+// (contract_r8), 16 transmit columns; wave w takes element quarter w (element pairs 2j, 2j+1
+// with j = w (mod 4)), all 8 bins; the quarters are summed at the end in a fixed order.  Two
+// workgroups share a CU (at most 256 registers per lane), so one's start and reduction overlap
+// the other's element loop.
+constexpr int kContractWaves = 4;
 constexpr int kContractThreads = kContractWaves * 64;
-// Element pairs whose operand loads are in flight per wave.
-constexpr int kDepth = 4;
-// Result staging: per transmit column, 16 angles x 8 bins x {Re, Im} floats and a pad of two
+// Element pairs whose operand loads are in flight per wave (fewer with more accumulators).
+template <int R8>
+constexpr int contract_depth() { return R8 <= 2 ? 4 : 3; }
+// Result staging: per transmit column, 8 R8 angles x 8 bins x {Re, Im} floats and a pad of two
 // (the 16 columns of a wave's row then fall in distinct banks).
-constexpr int kYColF = 16 * kBinBlock * 2 + 2;
-constexpr int kStageFloat2 = 32 * kYColF / 2;
+template <int R8>
+constexpr int contract_col_floats() { return 8 * R8 * kBinBlock * 2 + 2; }
 
 // Split-precision workgroup: the same tile; wave w takes bin pair w % 4 over half w / 4 of the
 // elements, the halves summed at the end, with the chunk's anchors staged in LDS.
@@ -50,8 +54,11 @@ static_assert(kSplitBuf >= 4096, "LDS buffer holds the half sums");
 // Anchor loads per thread of one chunk (16-byte pieces, 8 per element).
 constexpr int kAnchorLoads = (kAnchorChunk * 8 + kSplitThreads - 1) / kSplitThreads;
 
+// Complex product with a fixed rounding sequence (one product rounded, then one fused
+// multiply-add per component), so that every kernel instantiation rounds a phase the same way
+// and an angle's result does not depend on the angles computed beside it.
 __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
 // Raw buffer view of nbytes at p (gfx9 descriptor: 32-bit data format, no swizzle): loads take
@@ -94,7 +101,15 @@ struct PairLoads {
     float4 d[R8];
 };
 
-// Per bin block (8 bins), R8 x 8 receive angles and 32 transmit columns:
+// LDS floats of the contraction: partial sums of the element quarters (two wave slots), then
+// the result staging.
+template <int R8>
+constexpr int contract_lds_floats() {
+    return 2 * R8 * 2048 > kContractCols * contract_col_floats<R8>() ? 2 * R8 * 2048
+                                                                     : kContractCols * contract_col_floats<R8>();
+}
+
+// Per bin block (8 bins), R8 x 8 receive angles and 16 transmit columns:
 // Y_k[o][i] = sum_l W_k[o][l] X_k[l][i] on v_mfma_f32_16x16x4_f32, one instruction per bin,
 // 8-angle tile and element pair: A (16 x 4) row lane % 16 = {Re rows 0..7, Im rows 8..15} x 8
 // angles, column lane / 16 = (element e = lane / 32 of the pair, part q = lane / 16 % 2); B
@@ -107,23 +122,22 @@ struct PairLoads {
 //    (Im row, Im part), -Im W for (Re row, Im part), Im W for (Im row, Re part), i.e.
 //    Re(a' D_b) with a' = a, i a or -i a for the anchor a; D_b = D_1^b (b <= 3) or
 //    D_4 D_1^(b-4) (three products at most past the anchor).
+//  * The workgroup's angle tile rt covers 8-angle table tiles t8 = rt R8 + t (half t8 % 2 of
+//    the 16-angle table tile t8 / 2); tiles past the table re-read its last one (their rows
+//    lie past M and are not stored).
 //  * Elements past the last one re-read its spectrum and steps; their anchors lie past the end
 //    of the anchor view, whose loads then return zero (the element offset is in the
 //    bounds-checked vector offset).
-// LDS floats of the contraction: partial sums of the element quarters (four wave slots), then
-// the result staging.
-template <int R8>
-constexpr int contract_lds_floats() { return R8 * 8192 > 32 * kYColF ? R8 * 8192 : 32 * kYColF; }
-
 template <int R8>
 __device__ __forceinline__ void contract_body(const float2* __restrict__ X, const float4* __restrict__ d14,
                                               const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
                                               int M, int L, int ncol, int kpad, int kb, int rt, int ct,
                                               float* __restrict__ lds) {
+    constexpr int kDepth = contract_depth<R8>();
+    constexpr int kColF = contract_col_floats<R8>();
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int g = wave & 1, e4 = wave >> 1;
-    const int nrt = (M + 15) / 16;
+    const int e4 = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int nrt16 = (M + 15) / 16;
 
     floatx4 acc[R8][kBinBlock];
 #pragma unroll
@@ -133,19 +147,27 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
 
     // lane roles
     const int e = lane >> 5, q = (lane >> 4) & 1, rowtype = (lane >> 3) & 1, o8 = lane & 7;
-    const int icol = min(ct * 32 + g * 16 + (lane & 15), ntx - 1) - ct * 32;
+    const int c0 = ct * kContractCols;
+    const int icol = min(c0 + (lane & 15), ntx - 1) - c0;
     // element l of this lane's operands: spectrum at byte xlane + l xstride of
-    // X + spec_index(8 kb, 0, 32 ct) (padding columns past the last transmit, never written, read
-    // the last transmit's run; their results are discarded); steps at byte dlane + 256 t + 256 l
-    // of D14 + rt L 16; anchor at byte alane + 64 t + 128 l of Anc + (kb nrt + rt) L 16
+    // X + spec_index(8 kb, 0, c0) (padding columns past the last transmit, never written, read
+    // the last transmit's run; their results are discarded); steps at byte dlane + tile_d[t] +
+    // 256 l of D14; anchor at byte alane_t[t] + 128 l of its view
     const uint32_t xlane = (uint32_t)icol * 64 + (uint32_t)q * 32;
     const uint32_t dlane = (uint32_t)o8 * sizeof(float4) + (uint32_t)e * 256;  // + the pair's element
-    const uint32_t alane = (uint32_t)o8 * sizeof(float2);
     const size_t xstride = (size_t)ncol * kBinBlock * sizeof(float2);
     const __amdgpu_buffer_rsrc_t xv =
-        buffer_view(X + spec_index(kb * kBinBlock, 0, ct * 32, L, ncol), (uint32_t)(L * xstride));
-    const __amdgpu_buffer_rsrc_t dv = buffer_view(d14 + (size_t)rt * L * 16, (uint32_t)L * 256);
-    const __amdgpu_buffer_rsrc_t av = buffer_view(anc + ((size_t)kb * nrt + rt) * L * 16, (uint32_t)L * 128);
+        buffer_view(X + spec_index(kb * kBinBlock, 0, c0, L, ncol), (uint32_t)(L * xstride));
+    const __amdgpu_buffer_rsrc_t dv = buffer_view(d14, (uint32_t)nrt16 * L * 256);
+    __amdgpu_buffer_rsrc_t av[R8];
+    uint32_t tile_d[R8], alane_t[R8];
+#pragma unroll
+    for (int t = 0; t < R8; ++t) {
+        const int t8 = min(rt * R8 + t, 2 * nrt16 - 1);
+        tile_d[t] = (uint32_t)(t8 >> 1) * L * 256 + (uint32_t)(t8 & 1) * 128;
+        av[t] = buffer_view(anc + ((size_t)kb * nrt16 + (t8 >> 1)) * L * 16, (uint32_t)L * 128);
+        alane_t[t] = (uint32_t)o8 * sizeof(float2) + (uint32_t)(t8 & 1) * 64;
+    }
     const int last = L - 1;
     const uint32_t xlane_e = xlane + (uint32_t)e * (uint32_t)xstride;  // + the pair's element
     // pair j = elements 2j, 2j + 1 (lanes of element 1 one row further); pairs past the end
@@ -153,13 +175,14 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
     // last block the Nyquist block; the next table row), which the zero anchor of an element
     // past the last one cancels: anchors are read with the element in the bounds-checked vector
     // offset of their view, so that reads past it return zero
-    auto load_phase = [&](PairLoads<R8>& d, int j) {
+    auto load_phase_tile = [&](PairLoads<R8>& d, int t, int j) {
         const uint32_t r = (uint32_t)min(2 * j, last);
+        d.d[t] = buffer_load4(dv, dlane, tile_d[t] + r * 256);
+        d.a[t] = buffer_load2(av[t], alane_t[t] + (uint32_t)(2 * j + e) * 128, 0);
+    };
+    auto load_phase = [&](PairLoads<R8>& d, int j) {
 #pragma unroll
-        for (int t = 0; t < R8; ++t) {
-            d.d[t] = buffer_load4(dv, dlane + 128 * t, r * 256);
-            d.a[t] = buffer_load2(av, alane + 64 * t + (uint32_t)(2 * j + e) * 128, 0);
-        }
+        for (int t = 0; t < R8; ++t) load_phase_tile(d, t, j);
     };
     auto load_spectrum = [&](PairLoads<R8>& d, int j) {
         const uint32_t r = (uint32_t)min(2 * j, last);
@@ -175,9 +198,11 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
     // this wave's element pairs j = e4 + 4 t, t < nt, in whole steps of kDepth pairs
     const int npairs = (L + 1) >> 1;
     const int nt = max(0, (npairs - e4 + 3) >> 2);
-    // steps of kDepth pairs, two per pass of the loop (a pass's waits count the loads of both its
-    // halves, not only its own half's)
-    const int steps = 2 * ((nt + 2 * kDepth - 1) / (2 * kDepth));
+    // steps of kDepth pairs, kRounds per pass of the loop (with two, a pass's waits count the
+    // loads of both its halves, not only its own half's; one at R8 = 4 keeps the registers
+    // within 256)
+    constexpr int kRounds = R8 == 4 ? 1 : 2;
+    const int steps = kRounds * ((nt + kRounds * kDepth - 1) / (kRounds * kDepth));
     PairLoads<R8> buf[kDepth];
 #pragma unroll
     for (int u = 0; u < kDepth; ++u) {
@@ -188,9 +213,9 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
     // waits in the loop then count only the loop's own loads)
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     int j = e4;
-    for (int it = 0; it < steps; it += 2, j += 8 * kDepth) {
+    for (int it = 0; it < steps; it += kRounds, j += 4 * kRounds * kDepth) {
 #pragma unroll
-        for (int uu = 0; uu < 2 * kDepth; ++uu) {
+        for (int uu = 0; uu < kRounds * kDepth; ++uu) {
             const int u = uu % kDepth;
             const PairLoads<R8>& c = buf[u];
             // B operands of the 8 bins: (bin i, bin i + 4) from the lane's half runs
@@ -206,10 +231,12 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
                     bop[i + 4] = __uint_as_float(sw[1]);
                 }
             }
-            // A operands: Re(a' D_b), D_b = D_1^b (b < 4), D_4 D_1^(b-4)
-            float aop[R8][kBinBlock];
+            // per 8-angle tile: its A operands Re(a' D_b), D_b = D_1^b (b < 4), D_4 D_1^(b-4), then
+            // the tile's loads for the pair kDepth steps ahead (into the same registers), then its
+            // products
 #pragma unroll
             for (int t = 0; t < R8; ++t) {
+                float aop[kBinBlock];
                 const float2 a = c.a[t];
                 const float2 ap = rot ? make_float2(__uint_as_float(__float_as_uint(a.y) ^ sx),
                                                     __uint_as_float(__float_as_uint(a.x) ^ sy))
@@ -217,32 +244,29 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
                 const float2 d1 = make_float2(c.d[t].x, c.d[t].y), d4 = make_float2(c.d[t].z, c.d[t].w);
                 const float2 w1 = cmul2(ap, d1), w2 = cmul2(w1, d1);
                 const float2 w4 = cmul2(ap, d4), w5 = cmul2(w4, d1), w6 = cmul2(w5, d1);
-                aop[t][0] = ap.x;
-                aop[t][1] = w1.x;
-                aop[t][2] = w2.x;
-                aop[t][3] = w2.x * d1.x - w2.y * d1.y;
-                aop[t][4] = w4.x;
-                aop[t][5] = w5.x;
-                aop[t][6] = w6.x;
-                aop[t][7] = w6.x * d1.x - w6.y * d1.y;
-            }
-            // the buffer takes this wave's pair kDepth steps ahead (into the same registers: the
-            // phase operands now, the spectrum after the products that read its swapped copy)
-            __builtin_amdgcn_sched_barrier(0);
-            load_phase(buf[u], j + 4 * (uu + kDepth));
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int t = 0; t < R8; ++t)
+                aop[0] = ap.x;
+                aop[1] = w1.x;
+                aop[2] = w2.x;
+                aop[3] = __builtin_fmaf(w2.x, d1.x, -(w2.y * d1.y));
+                aop[4] = w4.x;
+                aop[5] = w5.x;
+                aop[6] = w6.x;
+                aop[7] = __builtin_fmaf(w6.x, d1.x, -(w6.y * d1.y));
+                __builtin_amdgcn_sched_barrier(0);
+                load_phase_tile(buf[u], t, j + 4 * (uu + kDepth));
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int b = 0; b < kBinBlock; ++b)
-                    acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[t][b], bop[b], acc[t][b], 0, 0, 0);
+                    acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[b], bop[b], acc[t][b], 0, 0, 0);
+            }
+            // the spectrum after the products that read its swapped copy
             __builtin_amdgcn_sched_barrier(0);
             load_spectrum(buf[u], j + 4 * (uu + kDepth));
             __builtin_amdgcn_sched_barrier(0);
         }
     }
     // element quarters summed as (q0 + q2) + (q1 + q3): quarters 2, 3 (then 1) hand their sums
-    // to the wave below through slot 2 g + (e4 & 1) of LDS
+    // to the wave two (then one) below through LDS slot e4 % 2
     constexpr int kSlot = R8 * kBinBlock * 4 * 64;  // floats per wave slot
     auto put = [&](int slot) {
         float* d = lds + slot * kSlot + lane;
@@ -262,18 +286,18 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[t][b][v] += d[((t * kBinBlock + b) * 4 + v) * 64];
     };
-    if (e4 >= 2) put(2 * g + (e4 & 1));
+    if (e4 >= 2) put(e4 & 1);
     __syncthreads();
-    if (e4 < 2) add(2 * g + e4);
+    if (e4 < 2) add(e4);
     __syncthreads();
-    if (e4 == 1) put(2 * g);
+    if (e4 == 1) put(0);
     __syncthreads();
-    if (e4 == 0) add(2 * g);
+    if (e4 == 0) add(0);
     __syncthreads();
     // results to LDS as [column][angle][bin][Re, Im], then out as 64-byte runs (8 bins of one
     // (i, o)), 8 threads per run
     if (e4 == 0) {
-        const int col = 16 * g + (lane & 15);
+        const int col = lane & 15;
         const int comp = lane >> 5, o4 = ((lane >> 4) & 1) * 4;
 #pragma unroll
         for (int t = 0; t < R8; ++t)
@@ -281,18 +305,19 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
             for (int b = 0; b < kBinBlock; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    lds[col * kYColF + ((8 * t + o4 + v) * kBinBlock + b) * 2 + comp] = acc[t][b][v];
+                    lds[col * kColF + ((8 * t + o4 + v) * kBinBlock + b) * 2 + comp] = acc[t][b][v];
     }
     __syncthreads();
     const float2* yst = reinterpret_cast<const float2*>(lds);
+    constexpr int kAng = 8 * R8;
 #pragma unroll
-    for (int u = 0; u < 32 * 16 * kBinBlock / kContractThreads; ++u) {
+    for (int u = 0; u < kContractCols * kAng * kBinBlock / kContractThreads; ++u) {
         const int f = tid + u * kContractThreads;  // float2 f & 7 of run f >> 3
         const int run = f >> 3, q8 = f & 7;
-        const int il = run >> 4, ol = run & 15;
-        const int i = ct * 32 + il, o = rt * 16 + ol;
-        if (ol < 8 * R8 && i < ntx && o < M)
-            Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q8] = yst[(il * kYColF) / 2 + ol * kBinBlock + q8];
+        const int il = run / kAng, ol = run % kAng;
+        const int i = c0 + il, o = rt * kAng + ol;
+        if (i < ntx && o < M)
+            Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q8] = yst[(il * kColF) / 2 + ol * kBinBlock + q8];
     }
 }
 
@@ -303,34 +328,14 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
 // v_mfma_f32_32x32x16_{bf16,f16} (eight complex elements per instruction: K = 8 elements x
 // {Re, Im}; lane l holds K slice 8 (l / 32) .. + 7, i.e. elements 4 (l / 32) .. + 3, of row or
 // column l % 32).  The dropped Wl Xl term and the residuals are below 2^-16 (BF16) or 2^-22
-// (FP16) of the terms.  FP16 spectra are first scaled by 2^e so that |X| < 2^15 (|X| <= 2 T
-// 32768 for int16 records), and Y by 2^-e (both exact).  Same workgroup shape, spectrum
-// layout and phase construction as the FP32 kernel.
+// (FP16) of the terms.  The forward transform stores the spectrum already split (its 8 bytes
+// per bin: the hi pair and the lo pair), so the B operands are loaded words; FP16 spectra are
+// scaled by 2^e before the split so that |X| < 2^15 (|X| <= 2 T 32768 for int16 records), and
+// Y by 2^-e here (both exact).  Workgroup: one bin block, 16 receive angles, 32 transmits;
+// wave w takes bin pair w % 4 over half w / 4 of the elements, the halves summed at the end.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-template <bool F16>
-__device__ __forceinline__ uint32_t half_bits(float x) {
-    if constexpr (F16)
-        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
-    else
-        return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x);
-}
-template <bool F16>
-__device__ __forceinline__ float half_value(float x) {
-    if constexpr (F16)
-        return (float)(_Float16)x;
-    else
-        return (float)(__bf16)x;
-}
-// (first, second) -> hi pair and lo pair, low half = first
-template <bool F16>
-__device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
-    const float ah = half_value<F16>(a), bh = half_value<F16>(b);
-    hi = half_bits<F16>(a) | (half_bits<F16>(b) << 16);
-    lo = half_bits<F16>(a - ah) | (half_bits<F16>(b - bh) << 16);
-}
 
 template <bool F16>
 __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
@@ -346,7 +351,7 @@ __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
 // anchors and the coefficients of the lane that holds (Re row, Re part) of its angle:
 // (Re D, -Im D) of both bins.
 struct SplitLoads {
-    float4 x[4];
+    float4 x[4];  // words of bins 2p, 2p + 1: (hi pair, lo pair, hi pair, lo pair)
     float2 a[4];
     float4 d[4];
 };
@@ -354,26 +359,35 @@ struct SplitLoads {
 template <bool F16>
 __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X, const float4* __restrict__ cf,
                                                     const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
-                                                    int M, int L, int ncol, int kpad, float xscale, float yscale,
-                                                    int kb, int rt, int ct) {
+                                                    int M, int L, int ncol, int kpad, float yscale, int kb,
+                                                    int rt, int ct) {
     __shared__ __attribute__((aligned(16))) float2 buf[kSplitBuf];
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int p = wave & 3, h = wave >> 2;
     const int g = lane >> 5, col = lane & 31, orow = col & 15;
-    const bool im_row = col >= 16;
     const int nrt = (M + 15) / 16;
 
     floatx16 acc0, acc1;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
 
-    const size_t xstride = (size_t)kBinBlock * ncol;  // complex floats between elements
-    // padding columns read the last transmit's spectrum (results discarded)
-    const float4* xp = reinterpret_cast<const float4*>(
-        X + spec_index(kb * kBinBlock + 2 * p, 0, min(ct * 32 + col, ntx - 1), L, ncol));
-    const float4* dp = cf + (size_t)(rt * 4 + p) * L * 64 + orow;
+    // the lane's element l = l0 + 4 g + e: spectrum words of bins 2p, 2p+1 at byte
+    // xlane + (l0 + e) xstride of X + spec_index(8 kb + 2p, 0, 32 ct) (padding columns read the
+    // last transmit's run, results discarded); coefficients at dlane + (l0 + e) 1024 of the
+    // (rt, p) slab of Cf (the lane's row entry of the Re part: (Re D, -Im D) for Re rows,
+    // (Im D, Re D) for Im rows, both bins);
+    // elements past the view read zeros, elements outside the wave's range enter with a zero
+    // anchor
+    const uint32_t xstride = (uint32_t)ncol * kBinBlock * sizeof(float2);
+    const int icol = min(ct * 32 + col, ntx - 1) - ct * 32;
+    const __amdgpu_buffer_rsrc_t xv =
+        buffer_view(X + spec_index(kb * kBinBlock + 2 * p, 0, ct * 32, L, ncol), (uint32_t)L * xstride);
+    const __amdgpu_buffer_rsrc_t dv = buffer_view(cf + (size_t)(rt * 4 + p) * L * 64, (uint32_t)L * 1024);
+    const uint32_t xlane = (uint32_t)icol * 64 + (uint32_t)(4 * g) * xstride;
+    const uint32_t dlane = (uint32_t)col * sizeof(float4) + (uint32_t)(4 * g) * 1024;
     const float2* ablk = anc + ((size_t)kb * nrt + rt) * L * 16;
+    constexpr int kSplitDepth = 3;  // groups of 8 elements whose loads are in flight per wave
 
     for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
         const int cn = min(kAnchorChunk, L - c0);
@@ -384,61 +398,74 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
         const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
         const int e1 = __builtin_amdgcn_readfirstlane(min(c0 + cn, e0 + half));
         const int last = e1 - 1;
-        auto load = [&](SplitLoads& q, int l0) {
+        auto load_coef = [&](SplitLoads& q, int l0) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int l = min(l0 + 4 * g + e, last);
-                q.x[e] = xp[(size_t)l * (xstride / 2)];
-                q.d[e] = dp[(size_t)l * 64];
-                q.a[e] = buf[(l - c0) * 16 + orow];
+                q.d[e] = buffer_load4(dv, dlane, (uint32_t)(l0 + e) * 1024);
+                q.a[e] = buf[min(l0 + 4 * g + e - c0, cn - 1) * 16 + orow];
             }
         };
-        if (e0 < e1) {
-            // whole groups of 8 elements, two groups of loads in flight; elements past the
-            // last one re-read it and enter with a zero phase
-            const int groups = (e1 - e0 + 7) / 8;
-            const int steps = (groups + 1) / 2;
-            SplitLoads q[2];
-            load(q[0], e0);
-            asm volatile("" ::: "memory");  // the prologue issues its loads in the loop's order
-            load(q[1], e0 + 8);
-            asm volatile("" ::: "memory");
-            int e = e0;
-            for (int it = 0; it < steps; ++it, e += 16) {
+        auto load_spectrum = [&](SplitLoads& q, int l0) {
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int l0 = e + 8 * u;
+            for (int e = 0; e < 4; ++e) q.x[e] = buffer_load4(xv, xlane, (uint32_t)(l0 + e) * xstride);
+        };
+        if (e0 < e1) {
+            // whole groups of 8 elements in steps of kSplitDepth groups, two steps per pass
+            const int groups = (e1 - e0 + 7) / 8;
+            const int steps = 2 * ((groups + 2 * kSplitDepth - 1) / (2 * kSplitDepth));
+            SplitLoads q[kSplitDepth];
+#pragma unroll
+            for (int u = 0; u < kSplitDepth; ++u) {
+                load_coef(q[u], e0 + 8 * u);
+                load_spectrum(q[u], e0 + 8 * u);
+            }
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loop counts only its own loads
+            int e = e0;
+            for (int it = 0; it < steps; it += 2, e += 16 * kSplitDepth) {
+#pragma unroll
+                for (int uu = 0; uu < 2 * kSplitDepth; ++uu) {
+                    const int u = uu % kSplitDepth;
+                    const int l0 = e + 8 * uu;
                     const SplitLoads& c = q[u];
-                    uint32_t hv[8][4];  // per element: A hi/lo of both bins, B hi/lo of both bins
+                    uint32_t hv[4][4];  // per element: A hi/lo of both bins
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const bool valid = l0 + 4 * g + k <= last;
                         const float2 an = valid ? c.a[k] : make_float2(0.f, 0.f);
-                        const float2 w0 = cmul2(an, make_float2(c.d[k].x, -c.d[k].y));
-                        const float2 w1 = cmul2(an, make_float2(c.d[k].z, -c.d[k].w));
-                        // A row pair: Re rows (Wr, -Wi), Im rows (Wi, Wr)
-                        split_pair<F16>(im_row ? w0.y : w0.x, im_row ? w0.x : -w0.y, hv[0][k], hv[1][k]);
-                        split_pair<F16>(im_row ? w1.y : w1.x, im_row ? w1.x : -w1.y, hv[2][k], hv[3][k]);
-                        const float4 x = c.x[k];
-                        split_pair<F16>(x.x * xscale, x.y * xscale, hv[4][k], hv[5][k]);
-                        split_pair<F16>(x.z * xscale, x.w * xscale, hv[6][k], hv[7][k]);
+                        // A row pair (Re rows (Wr, -Wi), Im rows (Wi, Wr)) from the lane's own
+                        // coefficient c: (Re(a) c.x + Im(a) c.y, Re(a) c.y - Im(a) c.x)
+                        const float4 cw = c.d[k];
+                        split16_pair<F16>(__builtin_fmaf(an.x, cw.x, an.y * cw.y),
+                                          __builtin_fmaf(an.x, cw.y, -(an.y * cw.x)), hv[0][k], hv[1][k]);
+                        split16_pair<F16>(__builtin_fmaf(an.x, cw.z, an.y * cw.w),
+                                          __builtin_fmaf(an.x, cw.w, -(an.y * cw.z)), hv[2][k], hv[3][k]);
                     }
                     const u32x4 ah0 = {hv[0][0], hv[0][1], hv[0][2], hv[0][3]};
                     const u32x4 al0 = {hv[1][0], hv[1][1], hv[1][2], hv[1][3]};
                     const u32x4 ah1 = {hv[2][0], hv[2][1], hv[2][2], hv[2][3]};
                     const u32x4 al1 = {hv[3][0], hv[3][1], hv[3][2], hv[3][3]};
-                    const u32x4 bh0 = {hv[4][0], hv[4][1], hv[4][2], hv[4][3]};
-                    const u32x4 bl0 = {hv[5][0], hv[5][1], hv[5][2], hv[5][3]};
-                    const u32x4 bh1 = {hv[6][0], hv[6][1], hv[6][2], hv[6][3]};
-                    const u32x4 bl1 = {hv[7][0], hv[7][1], hv[7][2], hv[7][3]};
-                    // this group's operands are in hv: the buffer takes the group two ahead
-                    load(q[u], l0 + 16);
+                    // B: the stored halves of bins 2p (x, y) and 2p + 1 (z, w) of the 4 elements
+                    const u32x4 bh0 = {__float_as_uint(c.x[0].x), __float_as_uint(c.x[1].x), __float_as_uint(c.x[2].x),
+                                       __float_as_uint(c.x[3].x)};
+                    const u32x4 bl0 = {__float_as_uint(c.x[0].y), __float_as_uint(c.x[1].y), __float_as_uint(c.x[2].y),
+                                       __float_as_uint(c.x[3].y)};
+                    const u32x4 bh1 = {__float_as_uint(c.x[0].z), __float_as_uint(c.x[1].z), __float_as_uint(c.x[2].z),
+                                       __float_as_uint(c.x[3].z)};
+                    const u32x4 bl1 = {__float_as_uint(c.x[0].w), __float_as_uint(c.x[1].w), __float_as_uint(c.x[2].w),
+                                       __float_as_uint(c.x[3].w)};
+                    // the buffer takes the group kSplitDepth ahead: coefficients and anchors now,
+                    // the spectrum after the products that read it
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_coef(q[u], l0 + 8 * kSplitDepth);
+                    __builtin_amdgcn_sched_barrier(0);
                     acc0 = mfma16<F16>(ah0, bl0, acc0);
                     acc0 = mfma16<F16>(al0, bh0, acc0);
                     acc0 = mfma16<F16>(ah0, bh0, acc0);
                     acc1 = mfma16<F16>(ah1, bl1, acc1);
                     acc1 = mfma16<F16>(al1, bh1, acc1);
                     acc1 = mfma16<F16>(ah1, bh1, acc1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_spectrum(q[u], l0 + 8 * kSplitDepth);
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -482,29 +509,41 @@ __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X
     }
 }
 
+// Bin block kb and angle tile rt of workgroup x of a launch over nkb x nrt such workgroups
+// (nkb a multiple of 8): the angle tiles of one bin block get ids 8 apart, so they land on one
+// XCD (workgroups are dealt to the 8 XCDs in turn) back to back and share its L2 for the
+// spectrum they all read.
+__device__ __forceinline__ void tile_of(int x, int nrt, int& kb, int& rt) {
+    kb = 8 * (x / (8 * nrt)) + (x & 7);
+    rt = (x >> 3) % nrt;
+}
+
 template <int R8>
-__global__ __launch_bounds__(kContractThreads) void contract_kernel(const float2* __restrict__ X,
-                                                                     const float4* __restrict__ d14,
-                                                                     const float2* __restrict__ anc,
-                                                                     float2* __restrict__ Y, int ntx, int M,
-                                                                     int L, int ncol, int kpad) {
+__global__ __launch_bounds__(kContractThreads, 2) void contract_kernel(const float2* __restrict__ X,
+                                                                        const float4* __restrict__ d14,
+                                                                        const float2* __restrict__ anc,
+                                                                        float2* __restrict__ Y, int ntx, int M,
+                                                                        int L, int ncol, int kpad) {
     __shared__ __attribute__((aligned(16))) float lds[contract_lds_floats<R8>()];
-    contract_body<R8>(X, d14, anc, Y, ntx, M, L, ncol, kpad, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+    int kb, rt;
+    tile_of(blockIdx.x, contract_angle_tiles(M), kb, rt);
+    contract_body<R8>(X, d14, anc, Y, ntx, M, L, ncol, kpad, kb, rt, blockIdx.z, lds);
 }
 
 template <bool F16>
 __global__ __launch_bounds__(kSplitThreads) void contract_split_kernel(
     const float2* __restrict__ X, const float4* __restrict__ cf, const float2* __restrict__ anc,
-    float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad, float xscale, float yscale) {
-    contract_split_body<F16>(X, cf, anc, Y, ntx, M, L, ncol, kpad, xscale, yscale, blockIdx.x, blockIdx.y,
-                             blockIdx.z);
+    float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad, float yscale) {
+    int kb, rt;
+    tile_of(blockIdx.x, (M + 15) / 16, kb, rt);
+    contract_split_body<F16>(X, cf, anc, Y, ntx, M, L, ncol, kpad, yscale, kb, rt, blockIdx.z);
 }
 
 // Grouped launches over the frames of one FFT-length class: block b runs block b - block0
 // of frame entry blk[b], in the per-frame grid order (bin block fastest, then receive tile,
 // then transmit tile).  PREC: 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo.
 template <int PREC>
-__global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads) void contract_grouped(
+__global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads, PREC == 0 ? 2 : 1) void contract_grouped(
     const ContractEntry* __restrict__ tab, const int32_t* __restrict__ blk, float2* __restrict__ ws) {
     const ContractEntry e = tab[blk[blockIdx.x]];
     int local = (int)blockIdx.x - e.block0;
@@ -513,20 +552,31 @@ __global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads) void 
     const int rt = local % e.nrt, ct = local / e.nrt;
     const PhaseTables pt{nullptr, e.M, reinterpret_cast<float4*>(ws + e.d_off)};
     if constexpr (PREC == 0) {
-        __shared__ __attribute__((aligned(16))) float lds[contract_lds_floats<2>()];
-        if (e.M <= 8)
-            contract_body<1>(ws + e.x_off, pt.d14(e.L), pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
-                             kb, rt, ct, lds);
-        else
-            contract_body<2>(ws + e.x_off, pt.d14(e.L), pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
-                             kb, rt, ct, lds);
+        __shared__ __attribute__((aligned(16))) float lds[contract_lds_floats<4>()];
+        const float4* d14 = pt.d14(e.L);
+        const float2* anc = pt.anc(e.L);
+        float2* X = ws + e.x_off;
+        float2* Y = ws + e.y_off;
+        switch (contract_r8(e.M)) {
+            case 1: contract_body<1>(X, d14, anc, Y, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct, lds); break;
+            case 2: contract_body<2>(X, d14, anc, Y, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct, lds); break;
+            case 3: contract_body<3>(X, d14, anc, Y, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct, lds); break;
+            default: contract_body<4>(X, d14, anc, Y, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct, lds); break;
+        }
     } else
         contract_split_body<PREC == 2>(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
-                                       e.xscale, e.yscale, kb, rt, ct);
+                                       e.yscale, kb, rt, ct);
 }
 
 // bins 0 .. n/2 - 1 (the Nyquist bin is summed by the inverse transform)
-dim3 contract_grid(int log2n, int M, int ncol) { return dim3(contract_bin_blocks(log2n), (M + 15) / 16, ncol / 32); }
+// FP32: bin blocks x angle tiles of 8 R8 x column groups of 16; split precision: bin blocks x
+// 16-angle tiles x column groups of 32
+// (x: bin blocks x angle tiles in tile_of order, z: column groups)
+dim3 contract_grid(int log2n, int precision, int M, int ntx, int ncol) {
+    if (precision == KK_PREC_FP32)
+        return dim3(contract_bin_blocks(log2n) * contract_angle_tiles(M), 1, (ntx + kContractCols - 1) / kContractCols);
+    return dim3(contract_bin_blocks(log2n) * ((M + 15) / 16), 1, ncol / 32);
+}
 
 }  // namespace
 
@@ -534,25 +584,37 @@ dim3 contract_grid(int log2n, int M, int ncol) { return dim3(contract_bin_blocks
 hipError_t launch_contract(int log2n, int precision, const float2* X, const PhaseTables& pt, float2* Y, int ntx,
                            int L, int ncol, int kpad, float xscale, hipStream_t st) {
     if (log2n < kMinLog2Fft || log2n > kMaxLog2Fft) return hipErrorInvalidValue;
-    const dim3 grid = contract_grid(log2n, pt.M, ncol);
+    const dim3 grid = contract_grid(log2n, precision, pt.M, ntx, ncol);
     const dim3 block(precision == KK_PREC_FP32 ? kContractThreads : kSplitThreads);
     const float2* anc = pt.anc(L);
     switch (precision) {
         case KK_PREC_FP32:
-            if (pt.M <= 8)
-                hipLaunchKernelGGL(contract_kernel<1>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L, ncol,
-                                   kpad);
-            else
-                hipLaunchKernelGGL(contract_kernel<2>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L, ncol,
-                                   kpad);
+            switch (contract_r8(pt.M)) {
+                case 1:
+                    hipLaunchKernelGGL(contract_kernel<1>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L,
+                                       ncol, kpad);
+                    break;
+                case 2:
+                    hipLaunchKernelGGL(contract_kernel<2>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L,
+                                       ncol, kpad);
+                    break;
+                case 3:
+                    hipLaunchKernelGGL(contract_kernel<3>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L,
+                                       ncol, kpad);
+                    break;
+                default:
+                    hipLaunchKernelGGL(contract_kernel<4>, grid, block, 0, st, X, pt.d14(L), anc, Y, ntx, pt.M, L,
+                                       ncol, kpad);
+                    break;
+            }
             break;
         case KK_PREC_BF16X3:
             hipLaunchKernelGGL((contract_split_kernel<false>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
-                               ncol, kpad, xscale, 1.0f / xscale);
+                               ncol, kpad, 1.0f / xscale);
             break;
         case KK_PREC_FP16X3:
             hipLaunchKernelGGL((contract_split_kernel<true>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
-                               ncol, kpad, xscale, 1.0f / xscale);
+                               ncol, kpad, 1.0f / xscale);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -623,10 +685,10 @@ hipError_t decompose_front(const int16_t* rf, int32_t N, const kk_geom* g, const
                            bool tables_ready = false) {
     float2* X = reinterpret_cast<float2*>(w + d.x_off);
     const PhaseTables pt{shift_q, M, reinterpret_cast<float4*>(w + d.d_off)};
-    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st,
-                                      tables_ready ? nullptr : &pt);
-    if (e != hipSuccess) return e;
     const float xscale = precision == KK_PREC_FP16X3 ? std::ldexp(1.0f, fp16_prescale_exponent(g->T)) : 1.0f;
+    hipError_t e = launch_fft_forward(rf, N * g->L, g->T, d.log2n, X, true, g->L, d.ncol, d.kpad, st,
+                                      tables_ready ? nullptr : &pt, precision, xscale);
+    if (e != hipSuccess) return e;
     return launch_contract(d.log2n, precision, X, pt, Y, N, g->L, d.ncol, d.kpad, xscale, st);
 }
 

@@ -246,6 +246,8 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
                 a.ncol = w.ncol;
                 a.kpad = w.kpad;
                 a.block0 = (int32_t)fb.size();
+                a.split = precision;
+                a.xscale = precision == KK_PREC_FP16X3 ? std::ldexp(1.0f, fp16_prescale_exponent(in.T)) : 1.0f;
                 // record pairs (transmits i, i+1 of one element), then the phase-table blocks
                 const int64_t nfb = (int64_t)in.L * ((in.N + 1) / 2) + phase_table_blocks(in.M, in.L, lg);
                 if (!check_blocks((int64_t)fb.size() + nfb)) return KK_E_ARG;
@@ -262,15 +264,14 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
                 c.ncol = w.ncol;
                 c.kpad = w.kpad;
                 c.nkb = (1 << lg) / 2 / kBinBlock;
-                c.nrt = (in.M + 15) / 16;
+                // FP32: angle tiles of 8 R8 and column groups of 16; split: 16 x 32
+                const bool fp32 = precision == KK_PREC_FP32;
+                c.nrt = fp32 ? contract_angle_tiles(in.M) : (in.M + 15) / 16;
                 c.block0 = (int32_t)cb.size();
-                c.xscale = c.yscale = 1.0f;
-                if (precision == KK_PREC_FP16X3) {
-                    const int ex = fp16_prescale_exponent(in.T);
-                    c.xscale = std::ldexp(1.0f, ex);
-                    c.yscale = std::ldexp(1.0f, -ex);
-                }
-                const int64_t ncb = (int64_t)c.nkb * c.nrt * (w.ncol / 32);
+                c.xscale = a.xscale;
+                c.yscale = 1.0f / a.xscale;
+                const int64_t ncb =
+                    (int64_t)c.nkb * c.nrt * (fp32 ? (in.N + kContractCols - 1) / kContractCols : w.ncol / 32);
                 if (!check_blocks((int64_t)cb.size() + ncb)) return KK_E_ARG;
                 cb.insert(cb.end(), (size_t)ncb, e);
                 ce.push_back(c);

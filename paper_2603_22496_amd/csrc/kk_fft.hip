@@ -309,10 +309,26 @@ __device__ __forceinline__ void phase_table_block(const int32_t* __restrict__ sh
 // records 2 blk, 2 blk + 1, and 64-byte runs (8 bins) of each record.
 // Body of block blk of one frame (shared by the per-frame and the grouped launches); blocked
 // launches carry the phase-table blocks after the record pairs.
+// Spectrum words of bins (k, k+1) = (v.x + i v.y, v.z + i v.w): FP32, or (split = BF16X3 or
+// FP16X3) each bin times xscale split in 16-bit halves as (hi pair, lo pair).
+__device__ __forceinline__ float4 spectrum_words(float4 v, int split, float xscale) {
+    if (split == 0) return v;
+    uint32_t h0, l0, h1, l1;
+    if (split == 2) {
+        split16_pair<true>(v.x * xscale, v.y * xscale, h0, l0);
+        split16_pair<true>(v.z * xscale, v.w * xscale, h1, l1);
+    } else {
+        split16_pair<false>(v.x * xscale, v.y * xscale, h0, l0);
+        split16_pair<false>(v.z * xscale, v.w * xscale, h1, l1);
+    }
+    return make_float4(__uint_as_float(h0), __uint_as_float(l0), __uint_as_float(h1), __uint_as_float(l1));
+}
+
 template <int LOG2N, bool BLOCKED>
 __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf, int ntraces, int T,
                                                  float2* __restrict__ out, int L, int ncol, int kpad, int blk,
-                                                 const int32_t* __restrict__ shift, int M, float4* __restrict__ cf) {
+                                                 const int32_t* __restrict__ shift, int M, float4* __restrict__ cf,
+                                                 int split = 0, float xscale = 1.0f) {
     using F = FftPlan<LOG2N>;
     constexpr int N = F::N;
     __shared__ __attribute__((aligned(16))) float2 data[N + N / 16 + 1];  // + the mirror slot of bin 0
@@ -394,10 +410,10 @@ __device__ __forceinline__ void fft_forward_body(const int16_t* __restrict__ rf,
                 B.x = z0.y;
                 B.y = 0.f;
             }
-            o[it * ostep] = A;
-            o[it * ostep + kBinBlock / 2] = B;
+            o[it * ostep] = spectrum_words(A, split, xscale);
+            o[it * ostep + kBinBlock / 2] = spectrum_words(B, split, xscale);
         }
-        if (tid == 0) {  // bin n/2 (read by the inverse transform's Nyquist sum), then a zero bin
+        if (tid == 0) {  // bin n/2 in FP32 (read by the inverse transform's Nyquist sum), then a zero bin
             const float2 z = data[pad(N / 2)];
             float4* q = reinterpret_cast<float4*>(out + spec_index(N / 2, l0, i0, L, ncol));
             q[0] = make_float4(z.x, 0.f, 0.f, 0.f);
@@ -547,8 +563,8 @@ template <int LOG2N, bool BLOCKED>
 __global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_forward_kernel(const int16_t* __restrict__ rf, int ntraces,
                                                                   int T, float2* __restrict__ out, int L, int ncol,
                                                                   int kpad, const int32_t* __restrict__ shift, int M,
-                                                                  float4* __restrict__ cf) {
-    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x, shift, M, cf);
+                                                                  float4* __restrict__ cf, int split, float xscale) {
+    fft_forward_body<LOG2N, BLOCKED>(rf, ntraces, T, out, L, ncol, kpad, blockIdx.x, shift, M, cf, split, xscale);
 }
 
 template <int LOG2N, bool NYQ>
@@ -569,7 +585,7 @@ __global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_forward_grouped(cons
     const FwdEntry e = tab[blk[blockIdx.x]];
     fft_forward_body<LOG2N, true>(rf + e.rf_off, e.ntraces, e.T, ws + e.x_off, e.L, e.ncol, e.kpad,
                                   (int)blockIdx.x - e.block0, plan + e.shift_off, e.M,
-                                  reinterpret_cast<float4*>(ws + e.d_off));
+                                  reinterpret_cast<float4*>(ws + e.d_off), e.split, e.xscale);
 }
 
 template <int LOG2N>
@@ -584,17 +600,17 @@ __global__ __launch_bounds__(fft_threads<LOG2N>()) void fft_inverse_grouped(cons
 
 template <int LOG2N>
 hipError_t fwd(const int16_t* rf, int ntraces, int T, float2* out, bool blocked, int L, int ncol, int kpad,
-               hipStream_t st, const PhaseTables* ph) {
+               hipStream_t st, const PhaseTables* ph, int split, float xscale) {
     if (blocked) {
         // one record pair (transmits i, i+1 of one element) per workgroup, then the phase tables
         const int64_t pairs = (int64_t)L * ((ntraces / L + 1) / 2);
         const int64_t pblocks = ph ? phase_table_blocks(ph->M, L, LOG2N) : 0;
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, true>), dim3((unsigned)(pairs + pblocks)), dim3(fft_threads<LOG2N>()), 0,
                            st, rf, ntraces, T, out, L, ncol, kpad, ph ? ph->shift : nullptr, ph ? ph->M : 0,
-                           ph ? ph->cf : nullptr);
+                           ph ? ph->cf : nullptr, split, xscale);
     } else {
         hipLaunchKernelGGL((fft_forward_kernel<LOG2N, false>), dim3((ntraces + 1) / 2), dim3(fft_threads<LOG2N>()), 0, st, rf,
-                           ntraces, T, out, L, ncol, kpad, nullptr, 0, nullptr);
+                           ntraces, T, out, L, ncol, kpad, nullptr, 0, nullptr, 0, 1.0f);
     }
     return hipGetLastError();
 }
@@ -613,14 +629,15 @@ hipError_t inv(const float2* in, int ntraces, int kpad, float2* out, int T, hipS
 }  // namespace
 
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
-                              int ncol, int kpad, hipStream_t st, const PhaseTables* ph) {
+                              int ncol, int kpad, hipStream_t st, const PhaseTables* ph, int split, float xscale) {
+    if (split < 0 || split > 2 || (split != 0 && !blocked)) return hipErrorInvalidValue;
     switch (log2n) {
-        case 8: return fwd<8>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
-        case 9: return fwd<9>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
-        case 10: return fwd<10>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
-        case 11: return fwd<11>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
-        case 12: return fwd<12>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
-        case 13: return fwd<13>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph);
+        case 8: return fwd<8>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph, split, xscale);
+        case 9: return fwd<9>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph, split, xscale);
+        case 10: return fwd<10>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph, split, xscale);
+        case 11: return fwd<11>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph, split, xscale);
+        case 12: return fwd<12>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph, split, xscale);
+        case 13: return fwd<13>(rf, ntraces, T, out, blocked, L, ncol, kpad, st, ph, split, xscale);
         default: return hipErrorInvalidValue;
     }
 }

@@ -11,9 +11,39 @@ namespace kk {
 // (complex float units, ncol = transmits padded to a multiple of 32): per block and element,
 // one 64-byte run of 8 bins per transmit column.  The forward FFT transforms transmits i and
 // i+1 of one element together, so its four threads of one block write one whole 128-byte
-// line; a contraction wave reads 16 bytes of every run of one block and element (the four
-// waves of its workgroup read the rest of the same lines).
+// line; an FP32 contraction wave reads whole runs.  For the split-precision contraction the
+// same 8 bytes of a bin hold its value split in 16-bit halves (split16_pair): the hi pair
+// (Re, Im) and the lo pair, each as one 32-bit word with Re in the low half.
 constexpr int kBinBlock = 8;
+
+// x = hi + lo with hi = round16(x), lo = round16(x - hi), round16 = BF16 or FP16 rounding to
+// nearest even: the bits of (hi of a, hi of b) and (lo of a, lo of b), a in the low halves.
+typedef float kk_float2v __attribute__((ext_vector_type(2)));
+typedef __bf16 kk_bf16x2v __attribute__((ext_vector_type(2)));
+typedef _Float16 kk_f16x2v __attribute__((ext_vector_type(2)));
+// (a, b) rounded to 16 bits each (one packed conversion), a in the low half
+template <bool F16>
+__device__ __forceinline__ uint32_t round16_pair(float a, float b) {
+    const kk_float2v v = {a, b};
+    if constexpr (F16)
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, kk_f16x2v));
+    else
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, kk_bf16x2v));
+}
+template <bool F16>
+__device__ __forceinline__ void split16_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
+    hi = round16_pair<F16>(a, b);
+    float ah, bh;
+    if constexpr (F16) {
+        const kk_f16x2v x = __builtin_bit_cast(kk_f16x2v, hi);
+        ah = (float)x[0];
+        bh = (float)x[1];
+    } else {
+        ah = __uint_as_float(hi << 16);
+        bh = __uint_as_float(hi & 0xffff0000u);
+    }
+    lo = round16_pair<F16>(a - ah, b - bh);  // a - ah is exact
+}
 
 __host__ __device__ inline size_t spec_index(int k, int l, int i, int L, int ncol) {
     return (((size_t)(k >> 3) * L + l) * ncol + i) * 8 + (k & 7);
@@ -33,6 +63,15 @@ __host__ __device__ inline size_t spec_index(int k, int l, int i, int L, int nco
 //     the first bin of block kb.
 // The anchor times the step of the bin's offset in its block gives the bin's phase.
 __host__ __device__ inline int contract_bin_blocks(int log2n) { return (1 << log2n) / 2 / kBinBlock; }
+// FP32 contraction tiling: R8 tiles of 8 receive angles per workgroup (all M angles in one
+// workgroup up to 32; beyond, 24 or 32 per workgroup, whichever pads fewer angles) and 16
+// transmit columns per workgroup.
+__host__ __device__ inline int contract_r8(int M) {
+    if (M <= 32) return (M + 7) / 8;
+    return 3 * ((M + 23) / 24) < 4 * ((M + 31) / 32) ? 3 : 4;
+}
+__host__ __device__ inline int contract_angle_tiles(int M) { return (M + 8 * contract_r8(M) - 1) / (8 * contract_r8(M)); }
+constexpr int kContractCols = 16;
 __host__ __device__ inline size_t phase_cf_floats4(int M, int L) {
     return (size_t)((M + 15) / 16) * 4 * (size_t)L * 64;
 }
@@ -86,10 +125,13 @@ inline int log2_exact(int64_t n) {
 //            records i and i+1 of element l share a workgroup, a missing partner record of
 //            an odd transmit count is written as zeros; of the last block only bin n/2 is
 //            written); the launch also writes the phase tables *ph of the contraction (extra
-//            workgroups, ahead of the record pairs), when ph is given
+//            workgroups, ahead of the record pairs), when ph is given; split = KK_PREC_BF16X3
+//            or KK_PREC_FP16X3 stores bins below n/2 times xscale split in 16-bit halves
+//            (bin n/2 stays FP32)
 //   else:    out[t * kpad + k]                                   (trace layout)
 hipError_t launch_fft_forward(const int16_t* rf, int ntraces, int T, int log2n, float2* out, bool blocked, int L,
-                              int ncol, int kpad, hipStream_t st, const PhaseTables* ph = nullptr);
+                              int ncol, int kpad, hipStream_t st, const PhaseTables* ph = nullptr, int split = 0,
+                              float xscale = 1.0f);
 
 // Where the Nyquist bin of record t = i * M + o is not stored but summed by the inverse
 // transform itself: Y[n/2] = sum_l exp(i pi shift[o][l] / 2^22) X[i][l][n/2] (Eq. 3 at k = n/2),
@@ -128,6 +170,8 @@ struct FwdEntry {
     int64_t d_off;           // workspace: phase tables of the contraction (float2 units)
     int32_t ntraces, T, L, ncol, kpad, block0;
     int32_t shift_off, M;    // plan: shift table [M][L]
+    int32_t split;           // spectrum format: KK_PREC_* of the contraction
+    float xscale;            // split-precision prescale of the spectrum
 };
 struct ContractEntry {
     int64_t x_off, y_off;    // workspace: spectra in, contracted spectra [N][M][kpad] out
@@ -153,7 +197,7 @@ struct ReduceEntry {
     int64_t inten_off;       // intensities [X][Z], or -1
     int32_t K, S, npix, mode, block0, pad;
 };
-static_assert(sizeof(FwdEntry) == 56 && sizeof(ContractEntry) == 72 && sizeof(InvEntry) == 56 &&
+static_assert(sizeof(FwdEntry) == 64 && sizeof(ContractEntry) == 72 && sizeof(InvEntry) == 56 &&
                   sizeof(GatherEntry) == 40 && sizeof(ReduceEntry) == 48,
               "work table layout");
 

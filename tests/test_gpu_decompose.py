@@ -59,6 +59,11 @@ def test_tiny_rf_theta(kk):
     (2, 9, 1024, 2, 1024, 4),     # record fills the whole FFT (no padding)
     (2, 4, 3000, 3, 4096, 5),
     (1, 3, 5000, 2, 8192, 6),
+    (3, 8, 500, 9, 512, 12),      # 16 angles per workgroup
+    (7, 10, 900, 29, 1024, 7),    # 32 angles per workgroup
+    (17, 11, 700, 40, 1024, 8),   # two 24-angle tiles, odd element count, one-column tail
+    (3, 5, 400, 64, 512, 10),     # two 32-angle tiles
+    (2, 4, 300, 100, 512, 11),    # five 24-angle tiles, the last past the phase tables
 ])
 def test_shapes_and_random_shifts(kk, N, L, T, M, tpad, seed):
     rng = np.random.default_rng(seed)
