@@ -500,62 +500,82 @@ def ensemble_report(kk, C, torch, np, args):
 
 
 def completion_report(kk, C, torch, np, args):
-    """k-space completion on the vernier geometry (13 of 128 bank columns observed): images of
-    evaluation phantoms (seeds 12000..) from plain compressed KK and from the completed spectrum,
-    against the fully sampled 128-angle KK image (GPU FP32, all pixels; FP64 oracle at sampled
-    pixels for two phantoms), with the trained weights committed in the package."""
+    """k-space completion on the vernier geometry, for each observed receive-angle set (13 of 128
+    bank columns: Eq. 6 j = 0, 15; Eq. 6 j = 0, 7, 15; Eq. 7): images of evaluation phantoms
+    (seeds 12000..) from plain compressed KK and from the completed spectrum, against the fully
+    sampled 128-angle KK image (GPU FP32, all pixels; FP64 oracle at sampled pixels for two
+    phantoms), with the trained weights committed in the package."""
     from paper_2603_22496_amd import completion as CP
     from oracle import frame as OF
-    cs = CP.setup()
-    d = CP.Device(cs)
-    loaded = CP.load()
-    W = len(cs.full.sel["rx_theta"])
-    net = kk.Net(loaded[0], CP.BATCH, cs.w.N, W, dilation=loaded[1].get("dilation")) if loaded else None
-    meta = loaded[1] if loaded else None
-    use_net = bool(meta and meta.get("use_net"))
-    errs = {"compressed": [], "compressed_best_gain": [], "completed": [], "completed_best_gain": []}
-    errs64 = {"compressed_best_gain": [], "completed": []}
-    rng = np.random.default_rng(5)
-    for e in range(args.completion_eval):
-        seed = CP.EVAL_SEED0 + e
-        ds = CP.phantom(cs, seed, meta["scatterers"] if meta else 1000)
-        rf = kk.to_device(ds.rf)
-        ref = CP.full_image(cs, d, rf).cpu().numpy()
-        comp = CP.complete_image(cs, d, rf, None).cpu().numpy()
-        a, b = CP.scaled_error(comp, ref)
-        errs["compressed"].append(a)
-        errs["compressed_best_gain"].append(b)
-        done = None
-        if net is not None:
-            done = CP.complete_image(cs, d, rf, net).cpu().numpy()
-            a, b = CP.scaled_error(done, ref)
-            errs["completed"].append(a)
-            errs["completed_best_gain"].append(b)
-        if e < 2 and not args.no_parity:   # the oracle checks the outputs; it produces none of them
-            xi, zi = rng.integers(0, cs.w.X, 300), rng.integers(0, cs.w.Z, 300)
-            sel_o, luts_o = OF.tables(cs.w, scheme=C.SCHEME_FULL_UNIFORM, M=len(cs.full.sel["rx_theta"]), j_list=(0,))
-            r64 = OF.kk_image(ds.rf, sel_o, luts_o, cs.w.X, cs.w.Z, pixels=(xi, zi))[0]
-            errs64["compressed_best_gain"].append(CP.scaled_error(comp[0, xi, zi], r64)[1])
-            if done is not None:
-                errs64["completed"].append(CP.scaled_error(done[0, xi, zi], r64)[0])
-    rf = kk.to_device(CP.phantom(cs, CP.EVAL_SEED0, 300).rf)
-    ms_c = timed(lambda: CP.complete_image(cs, d, rf, None), 5, 2, torch)
-    ms_n = timed(lambda: CP.complete_image(cs, d, rf, net), 3, 1, torch) if net is not None else None
     mean = lambda v: round(float(np.mean(v)), 4) if v else None
-    out = {
+    sets, first = {}, None
+    rng = np.random.default_rng(5)
+    pix = [(rng.integers(0, C.VERNIER.X, 300), rng.integers(0, C.VERNIER.Z, 300)) for _ in range(2)]
+    refs, refs64 = {}, {}
+    for name in CP.OBSERVED:
+        cs = CP.setup(observed=name)
+        d = CP.Device(cs)
+        loaded = CP.load(CP.weights_path(name))
+        W = len(cs.full.sel["rx_theta"])
+        net = kk.Net(loaded[0], CP.BATCH, cs.w.N, W, dilation=loaded[1].get("dilation")) if loaded else None
+        meta = loaded[1] if loaded else None
+        use_net = bool(meta and meta.get("use_net"))
+        errs = {"compressed": [], "compressed_best_gain": [], "completed": [], "completed_best_gain": []}
+        errs64 = {"compressed_best_gain": [], "completed": [], "completed_best_gain": []}
+        for e in range(args.completion_eval):
+            seed = CP.EVAL_SEED0 + e
+            ds = CP.phantom(cs, seed, meta["scatterers"] if meta else 1000)
+            rf = kk.to_device(ds.rf)
+            if seed not in refs:
+                refs[seed] = CP.full_image(cs, d, rf).cpu().numpy()
+            ref = refs[seed]
+            comp = CP.complete_image(cs, d, rf, None).cpu().numpy()
+            a, b = CP.scaled_error(comp, ref)
+            errs["compressed"].append(a)
+            errs["compressed_best_gain"].append(b)
+            done = None
+            if net is not None:
+                done = CP.complete_image(cs, d, rf, net).cpu().numpy()
+                a, b = CP.scaled_error(done, ref)
+                errs["completed"].append(a)
+                errs["completed_best_gain"].append(b)
+            if e < 2 and not args.no_parity:   # the oracle checks the outputs; it produces none of them
+                xi, zi = pix[e]
+                if seed not in refs64:
+                    sel_o, luts_o = OF.tables(cs.w, scheme=C.SCHEME_FULL_UNIFORM, M=W, j_list=(0,))
+                    refs64[seed] = OF.kk_image(ds.rf, sel_o, luts_o, cs.w.X, cs.w.Z, pixels=(xi, zi))[0]
+                r64 = refs64[seed]
+                errs64["compressed_best_gain"].append(CP.scaled_error(comp[0, xi, zi], r64)[1])
+                if done is not None:
+                    a, b = CP.scaled_error(done[0, xi, zi], r64)
+                    errs64["completed"].append(a)
+                    errs64["completed_best_gain"].append(b)
+        out = {
+            "selection": "Eq. %d, %s" % (7 if CP.OBSERVED[name][0] == C.SCHEME_CONFOCAL else 6,
+                                         "M = %d, j = %s" % (CP.OBSERVED[name][1], list(CP.OBSERVED[name][2]))),
+            "observed_columns": cs.cols.tolist(),
+            "rel_l2_vs_fully_sampled_gpu": {k: mean(v) for k, v in errs.items()},
+            "rel_l2_vs_fp64_fully_sampled_sampled_pixels": {k: mean(v) for k, v in errs64.items()},
+            "product_path": "network" if use_net else "fallback: plain compressed KK",
+        }
+        if meta:
+            out["training"] = {k: meta[k] for k in ("fit_phantoms", "validation_phantoms", "scatterers", "epochs",
+                                                    "bins_per_phantom", "batch", "seconds", "validation")}
+            out["training"]["final_loss"] = meta["history"][-1] if meta.get("history") else None
+        if first is None:
+            rf = kk.to_device(CP.phantom(cs, CP.EVAL_SEED0, 300).rf)
+            ms_c = timed(lambda: CP.complete_image(cs, d, rf, None), 5, 2, torch)
+            ms_n = timed(lambda: CP.complete_image(cs, d, rf, net), 3, 1, torch) if net is not None else None
+            first = {"compressed": round(ms_c, 3), "completed": round(ms_n, 3) if ms_n else None}
+        sets[name] = out
+        del d
+    return {
         "workload": "vernier geometry (128 el, 31 tx, 2048 samples, 256x512 px); 128-angle bank, 13 columns "
                     "observed (403 of 3968 pairs, 9.8x); 6x3x3 conv, 32 ch, BF16/FP32 on MFMA",
         "eval_phantoms": args.completion_eval,
-        "rel_l2_vs_fully_sampled_gpu": {k: mean(v) for k, v in errs.items()},
-        "rel_l2_vs_fp64_fully_sampled_sampled_pixels": {k: mean(v) for k, v in errs64.items()},
-        "product_path": "network" if use_net else "fallback: plain compressed KK",
-        "ms_per_frame": {"compressed": round(ms_c, 3), "completed": round(ms_n, 3) if ms_n else None},
+        "observed_sets": sets,
+        "ms_per_frame_vernier_set": first,
     }
-    if meta:
-        out["training"] = {k: meta[k] for k in ("fit_phantoms", "validation_phantoms", "scatterers", "epochs",
-                                                "bins_per_phantom", "batch", "seconds", "validation")}
-        out["training"]["final_loss"] = meta["history"][-1] if meta.get("history") else None
-    return out
 
 
 def study_report(np):
@@ -804,7 +824,8 @@ def main():
     if not args.no_completion:
         res["completion"] = section("completion", lambda: completion_report(kk, C, torch, np, args))
         if "error" not in res["completion"]:
-            log("completion %s" % json.dumps(res["completion"]["rel_l2_vs_fully_sampled_gpu"]))
+            for name, o in res["completion"]["observed_sets"].items():
+                log("completion %s %s" % (name, json.dumps(o["rel_l2_vs_fully_sampled_gpu"])))
 
     if not args.no_study:
         res["study"] = section("study", lambda: study_report(np))
