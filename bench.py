@@ -43,6 +43,8 @@ METRIC = "KK beamform Gpixel·pair/s and frames/s vs GPU DAS at rel-L2 ≤1e-5 (
 # index and fraction, four for the complex interpolate-accumulate, one address operation.
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 OPS_PER_PIXEL_PAIR = 8
+# Eq. 4's receive delay is not separable in (x, z): one more add per pixel*(transmit, element)
+DAS_OPS_PER_GATHER = 9
 HBM_BYTES_PER_S = 8.0e12
 MFMA_FP32_FLOPS = 157.3e12
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gather_vernier_traffic.md")
@@ -934,9 +936,9 @@ def main():
             out[name] = res[key]
     if "das_ms" in res:
         das_units = w.X * w.Z * w.N * w.L                 # pixel x (transmit, element) gathers
-        das_frac = round(OPS_PER_PIXEL_PAIR * das_units / VALU_LANE_OPS / (res["das_ms"] * 1e-3), 4)
+        das_frac = round(DAS_OPS_PER_GATHER * das_units / VALU_LANE_OPS / (res["das_ms"] * 1e-3), 4)
         out["stage_rooflines"]["das"] = {
-            "bound": "alu", "time_us": round(res["das_ms"] * 1e3, 2), "lane_ops": OPS_PER_PIXEL_PAIR * das_units,
+            "bound": "alu", "time_us": round(res["das_ms"] * 1e3, 2), "lane_ops": DAS_OPS_PER_GATHER * das_units,
             "frac": das_frac, "note": "analytic transforms and the DAS gather, against the gather's VALU bound"}
         out["das_frames_per_s"] = round(1e3 / res["das_ms"], 1)
         out["stages_us"]["das"] = round(res["das_ms"] * 1e3, 2)
