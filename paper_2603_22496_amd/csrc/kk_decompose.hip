@@ -43,15 +43,21 @@ constexpr int contract_depth() { return R8 <= 2 ? 4 : 3; }
 template <int R8>
 constexpr int contract_col_floats() { return 8 * R8 * kBinBlock * 2 + 2; }
 
-// Split-precision workgroup: the same tile; wave w takes bin pair w % 4 over half w / 4 of the
-// elements, the halves summed at the end, with the chunk's anchors staged in LDS.
-constexpr int kSplitWaves = 8;
+// Split-precision workgroup: one bin block, T16 tiles of 16 receive angles (T16 = 2 when
+// M > 16, so up to 32 angles share one pass over the spectrum), 32 transmit columns; wave w
+// takes bin pair w over all elements.  Two workgroups share a CU.
+constexpr int kSplitWaves = 4;
 constexpr int kSplitThreads = kSplitWaves * 64;
 constexpr int kAnchorChunk = 256;
-constexpr int kYCol = 16 * kBinBlock + 1;  // split kernel's staging: float2 per (column, angle, bin) + pad
-constexpr int kSplitBuf = kAnchorChunk * 16 > 32 * kYCol ? kAnchorChunk * 16 : 32 * kYCol;
-static_assert(kSplitBuf >= 4096, "LDS buffer holds the half sums");
-// Anchor loads per thread of one chunk (16-byte pieces, 8 per element).
+__host__ __device__ constexpr int split_t16(int M) { return M > 16 ? 2 : 1; }
+// staging of the results: float2 per (column, angle, bin) + a pad per column
+template <int T16>
+constexpr int split_col_float2() { return 16 * T16 * kBinBlock + 1; }
+template <int T16>
+constexpr int split_lds_float2() {
+    return T16 * kAnchorChunk * 16 > 32 * split_col_float2<T16>() ? T16 * kAnchorChunk * 16 : 32 * split_col_float2<T16>();
+}
+// Anchor loads per thread of one chunk and tile (16-byte pieces, 8 per element).
 constexpr int kAnchorLoads = (kAnchorChunk * 8 + kSplitThreads - 1) / kSplitThreads;
 
 // Complex product with a fixed rounding sequence (one product rounded, then one fused
@@ -347,165 +353,160 @@ __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c) {
                                                        c, 0, 0, 0);
 }
 
-// Loads of one group of 8 elements for one lane: its 4 elements' spectra (bins 2p and 2p+1),
-// anchors and the coefficients of the lane that holds (Re row, Re part) of its angle:
-// (Re D, -Im D) of both bins.
+// Loads of one group of 8 elements for one lane: its 4 elements' spectrum words (bins 2p and
+// 2p+1), and per 16-angle tile the anchors and the lane's own coefficients of both bins.
+template <int T16>
 struct SplitLoads {
     float4 x[4];  // words of bins 2p, 2p + 1: (hi pair, lo pair, hi pair, lo pair)
-    float2 a[4];
-    float4 d[4];
+    float2 a[T16][4];
+    float4 d[T16][4];
 };
 
-template <bool F16>
+template <bool F16, int T16>
 __device__ __forceinline__ void contract_split_body(const float2* __restrict__ X, const float4* __restrict__ cf,
                                                     const float2* __restrict__ anc, float2* __restrict__ Y, int ntx,
                                                     int M, int L, int ncol, int kpad, float yscale, int kb,
-                                                    int rt, int ct) {
-    __shared__ __attribute__((aligned(16))) float2 buf[kSplitBuf];
+                                                    int rt, int ct, float2* __restrict__ buf) {
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int p = wave & 3, h = wave >> 2;
+    const int p = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int g = lane >> 5, col = lane & 31, orow = col & 15;
-    const int nrt = (M + 15) / 16;
+    const int nrt16 = (M + 15) / 16;
 
-    floatx16 acc0, acc1;
+    floatx16 acc[T16][2];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
+    for (int t = 0; t < T16; ++t)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[t][0][v] = acc[t][1][v] = 0.0f;
 
     // the lane's element l = l0 + 4 g + e: spectrum words of bins 2p, 2p+1 at byte
     // xlane + (l0 + e) xstride of X + spec_index(8 kb + 2p, 0, 32 ct) (padding columns read the
     // last transmit's run, results discarded); coefficients at dlane + (l0 + e) 1024 of the
-    // (rt, p) slab of Cf (the lane's row entry of the Re part: (Re D, -Im D) for Re rows,
-    // (Im D, Re D) for Im rows, both bins);
-    // elements past the view read zeros, elements outside the wave's range enter with a zero
-    // anchor
+    // (tile, p) slab of Cf (the lane's row entry of the Re part: (Re D, -Im D) for Re rows,
+    // (Im D, Re D) for Im rows, both bins); past the last element the wave-uniform part of the
+    // element offset stays at the last one, so a lane reads at most 4 rows past its slab (the
+    // next bin block or the Nyquist block of the spectrum, the next table slab), and those
+    // elements enter with a zero anchor
     const uint32_t xstride = (uint32_t)ncol * kBinBlock * sizeof(float2);
     const int icol = min(ct * 32 + col, ntx - 1) - ct * 32;
     const __amdgpu_buffer_rsrc_t xv =
         buffer_view(X + spec_index(kb * kBinBlock + 2 * p, 0, ct * 32, L, ncol), (uint32_t)L * xstride);
-    const __amdgpu_buffer_rsrc_t dv = buffer_view(cf + (size_t)(rt * 4 + p) * L * 64, (uint32_t)L * 1024);
+    __amdgpu_buffer_rsrc_t dv[T16];
+    const float2* ablk[T16];
+#pragma unroll
+    for (int t = 0; t < T16; ++t) {
+        const int r16 = min(rt * T16 + t, nrt16 - 1);  // tiles past the table re-read its last one
+        dv[t] = buffer_view(cf + (size_t)(r16 * 4 + p) * L * 64, (uint32_t)L * 1024);
+        ablk[t] = anc + ((size_t)kb * nrt16 + r16) * L * 16;
+    }
     const uint32_t xlane = (uint32_t)icol * 64 + (uint32_t)(4 * g) * xstride;
     const uint32_t dlane = (uint32_t)col * sizeof(float4) + (uint32_t)(4 * g) * 1024;
-    const float2* ablk = anc + ((size_t)kb * nrt + rt) * L * 16;
-    constexpr int kSplitDepth = 3;  // groups of 8 elements whose loads are in flight per wave
+    constexpr int kSplitDepth = 2;  // groups of 8 elements whose loads are in flight per wave
 
     for (int c0 = 0; c0 < L; c0 += kAnchorChunk) {
         const int cn = min(kAnchorChunk, L - c0);
         __syncthreads();
-        stage_anchors(buf, ablk, c0, cn, tid);
+#pragma unroll
+        for (int t = 0; t < T16; ++t) stage_anchors(buf + t * kAnchorChunk * 16, ablk[t], c0, cn, tid);
         __syncthreads();
-        const int half = (cn + 1) >> 1;
-        const int e0 = __builtin_amdgcn_readfirstlane(c0 + h * half);
-        const int e1 = __builtin_amdgcn_readfirstlane(min(c0 + cn, e0 + half));
-        const int last = e1 - 1;
-        auto load_coef = [&](SplitLoads& q, int l0) {
+        const int last = c0 + cn - 1;
+        auto load_coef = [&](SplitLoads<T16>& q, int l0) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                q.d[e] = buffer_load4(dv, dlane, (uint32_t)(l0 + e) * 1024);
-                q.a[e] = buf[min(l0 + 4 * g + e - c0, cn - 1) * 16 + orow];
-            }
+            for (int t = 0; t < T16; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    q.d[t][e] = buffer_load4(dv[t], dlane, (uint32_t)min(l0 + e, L - 1) * 1024);
+                    q.a[t][e] = buf[t * kAnchorChunk * 16 + min(l0 + 4 * g + e - c0, cn - 1) * 16 + orow];
+                }
         };
-        auto load_spectrum = [&](SplitLoads& q, int l0) {
+        auto load_spectrum = [&](SplitLoads<T16>& q, int l0) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) q.x[e] = buffer_load4(xv, xlane, (uint32_t)(l0 + e) * xstride);
+            for (int e = 0; e < 4; ++e) q.x[e] = buffer_load4(xv, xlane, (uint32_t)min(l0 + e, L - 1) * xstride);
         };
-        if (e0 < e1) {
-            // whole groups of 8 elements in steps of kSplitDepth groups, two steps per pass
-            const int groups = (e1 - e0 + 7) / 8;
-            const int steps = 2 * ((groups + 2 * kSplitDepth - 1) / (2 * kSplitDepth));
-            SplitLoads q[kSplitDepth];
+        // whole groups of 8 elements in steps of kSplitDepth groups, two steps per pass
+        const int groups = (cn + 7) / 8;
+        const int steps = 2 * ((groups + 2 * kSplitDepth - 1) / (2 * kSplitDepth));
+        SplitLoads<T16> q[kSplitDepth];
 #pragma unroll
-            for (int u = 0; u < kSplitDepth; ++u) {
-                load_coef(q[u], e0 + 8 * u);
-                load_spectrum(q[u], e0 + 8 * u);
-            }
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loop counts only its own loads
-            int e = e0;
-            for (int it = 0; it < steps; it += 2, e += 16 * kSplitDepth) {
+        for (int u = 0; u < kSplitDepth; ++u) {
+            load_coef(q[u], c0 + 8 * u);
+            load_spectrum(q[u], c0 + 8 * u);
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the loop counts only its own loads
+        int e = c0;
+        for (int it = 0; it < steps; it += 2, e += 16 * kSplitDepth) {
 #pragma unroll
-                for (int uu = 0; uu < 2 * kSplitDepth; ++uu) {
-                    const int u = uu % kSplitDepth;
-                    const int l0 = e + 8 * uu;
-                    const SplitLoads& c = q[u];
-                    uint32_t hv[4][4];  // per element: A hi/lo of both bins
+            for (int uu = 0; uu < 2 * kSplitDepth; ++uu) {
+                const int u = uu % kSplitDepth;
+                const int l0 = e + 8 * uu;
+                const SplitLoads<T16>& c = q[u];
+                // B: the stored halves of bins 2p (x, y) and 2p + 1 (z, w) of the 4 elements
+                const u32x4 bh0 = {__float_as_uint(c.x[0].x), __float_as_uint(c.x[1].x), __float_as_uint(c.x[2].x),
+                                   __float_as_uint(c.x[3].x)};
+                const u32x4 bl0 = {__float_as_uint(c.x[0].y), __float_as_uint(c.x[1].y), __float_as_uint(c.x[2].y),
+                                   __float_as_uint(c.x[3].y)};
+                const u32x4 bh1 = {__float_as_uint(c.x[0].z), __float_as_uint(c.x[1].z), __float_as_uint(c.x[2].z),
+                                   __float_as_uint(c.x[3].z)};
+                const u32x4 bl1 = {__float_as_uint(c.x[0].w), __float_as_uint(c.x[1].w), __float_as_uint(c.x[2].w),
+                                   __float_as_uint(c.x[3].w)};
+                // per tile: A row pairs (Re rows (Wr, -Wi), Im rows (Wi, Wr)) from the anchor and the
+                // lane's coefficient c, (Re(a) c.x + Im(a) c.y, Re(a) c.y - Im(a) c.x), split
+                uint32_t hv[T16][4][4];
+#pragma unroll
+                for (int t = 0; t < T16; ++t)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const bool valid = l0 + 4 * g + k <= last;
-                        const float2 an = valid ? c.a[k] : make_float2(0.f, 0.f);
-                        // A row pair (Re rows (Wr, -Wi), Im rows (Wi, Wr)) from the lane's own
-                        // coefficient c: (Re(a) c.x + Im(a) c.y, Re(a) c.y - Im(a) c.x)
-                        const float4 cw = c.d[k];
+                        const float2 an = l0 + 4 * g + k <= last ? c.a[t][k] : make_float2(0.f, 0.f);
+                        const float4 cw = c.d[t][k];
                         split16_pair<F16>(__builtin_fmaf(an.x, cw.x, an.y * cw.y),
-                                          __builtin_fmaf(an.x, cw.y, -(an.y * cw.x)), hv[0][k], hv[1][k]);
+                                          __builtin_fmaf(an.x, cw.y, -(an.y * cw.x)), hv[t][0][k], hv[t][1][k]);
                         split16_pair<F16>(__builtin_fmaf(an.x, cw.z, an.y * cw.w),
-                                          __builtin_fmaf(an.x, cw.w, -(an.y * cw.z)), hv[2][k], hv[3][k]);
+                                          __builtin_fmaf(an.x, cw.w, -(an.y * cw.z)), hv[t][2][k], hv[t][3][k]);
                     }
-                    const u32x4 ah0 = {hv[0][0], hv[0][1], hv[0][2], hv[0][3]};
-                    const u32x4 al0 = {hv[1][0], hv[1][1], hv[1][2], hv[1][3]};
-                    const u32x4 ah1 = {hv[2][0], hv[2][1], hv[2][2], hv[2][3]};
-                    const u32x4 al1 = {hv[3][0], hv[3][1], hv[3][2], hv[3][3]};
-                    // B: the stored halves of bins 2p (x, y) and 2p + 1 (z, w) of the 4 elements
-                    const u32x4 bh0 = {__float_as_uint(c.x[0].x), __float_as_uint(c.x[1].x), __float_as_uint(c.x[2].x),
-                                       __float_as_uint(c.x[3].x)};
-                    const u32x4 bl0 = {__float_as_uint(c.x[0].y), __float_as_uint(c.x[1].y), __float_as_uint(c.x[2].y),
-                                       __float_as_uint(c.x[3].y)};
-                    const u32x4 bh1 = {__float_as_uint(c.x[0].z), __float_as_uint(c.x[1].z), __float_as_uint(c.x[2].z),
-                                       __float_as_uint(c.x[3].z)};
-                    const u32x4 bl1 = {__float_as_uint(c.x[0].w), __float_as_uint(c.x[1].w), __float_as_uint(c.x[2].w),
-                                       __float_as_uint(c.x[3].w)};
-                    // the buffer takes the group kSplitDepth ahead: coefficients and anchors now,
-                    // the spectrum after the products that read it
-                    __builtin_amdgcn_sched_barrier(0);
-                    load_coef(q[u], l0 + 8 * kSplitDepth);
-                    __builtin_amdgcn_sched_barrier(0);
-                    acc0 = mfma16<F16>(ah0, bl0, acc0);
-                    acc0 = mfma16<F16>(al0, bh0, acc0);
-                    acc0 = mfma16<F16>(ah0, bh0, acc0);
-                    acc1 = mfma16<F16>(ah1, bl1, acc1);
-                    acc1 = mfma16<F16>(al1, bh1, acc1);
-                    acc1 = mfma16<F16>(ah1, bh1, acc1);
-                    __builtin_amdgcn_sched_barrier(0);
-                    load_spectrum(q[u], l0 + 8 * kSplitDepth);
-                    __builtin_amdgcn_sched_barrier(0);
+                // the buffer takes the group kSplitDepth ahead: coefficients and anchors now, the
+                // spectrum after the products that read it
+                __builtin_amdgcn_sched_barrier(0);
+                load_coef(q[u], l0 + 8 * kSplitDepth);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < T16; ++t) {
+                    const u32x4 ah0 = {hv[t][0][0], hv[t][0][1], hv[t][0][2], hv[t][0][3]};
+                    const u32x4 al0 = {hv[t][1][0], hv[t][1][1], hv[t][1][2], hv[t][1][3]};
+                    const u32x4 ah1 = {hv[t][2][0], hv[t][2][1], hv[t][2][2], hv[t][2][3]};
+                    const u32x4 al1 = {hv[t][3][0], hv[t][3][1], hv[t][3][2], hv[t][3][3]};
+                    acc[t][0] = mfma16<F16>(ah0, bl0, acc[t][0]);
+                    acc[t][0] = mfma16<F16>(al0, bh0, acc[t][0]);
+                    acc[t][0] = mfma16<F16>(ah0, bh0, acc[t][0]);
+                    acc[t][1] = mfma16<F16>(ah1, bl1, acc[t][1]);
+                    acc[t][1] = mfma16<F16>(al1, bh1, acc[t][1]);
+                    acc[t][1] = mfma16<F16>(ah1, bh1, acc[t][1]);
                 }
+                __builtin_amdgcn_sched_barrier(0);
+                load_spectrum(q[u], l0 + 8 * kSplitDepth);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
+    // results to LDS as [column][angle][bin], then out as 64-byte runs (8 bins of one (i, o))
+    constexpr int kCol = split_col_float2<T16>();
     __syncthreads();
-    float* red = reinterpret_cast<float*>(buf);
-    if (h == 1) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            red[((p * 2 + 0) * 16 + v) * 64 + lane] = acc0[v];
-            red[((p * 2 + 1) * 16 + v) * 64 + lane] = acc1[v];
-        }
-    }
-    __syncthreads();
-    if (h == 0) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            acc0[v] += red[((p * 2 + 0) * 16 + v) * 64 + lane];
-            acc1[v] += red[((p * 2 + 1) * 16 + v) * 64 + lane];
-        }
-    }
-    __syncthreads();
-    float2* yst = buf;
-    if (h == 0) {
+    for (int t = 0; t < T16; ++t)
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-            const int ol = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-            yst[col * kYCol + ol * kBinBlock + 2 * p] = make_float2(acc0[v] * yscale, acc0[v + 8] * yscale);
-            yst[col * kYCol + ol * kBinBlock + 2 * p + 1] = make_float2(acc1[v] * yscale, acc1[v + 8] * yscale);
+            const int ol = 16 * t + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+            buf[col * kCol + ol * kBinBlock + 2 * p] = make_float2(acc[t][0][v] * yscale, acc[t][0][v + 8] * yscale);
+            buf[col * kCol + ol * kBinBlock + 2 * p + 1] =
+                make_float2(acc[t][1][v] * yscale, acc[t][1][v + 8] * yscale);
         }
-    }
     __syncthreads();
+    constexpr int kAng = 16 * T16;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 32 * kAng * kBinBlock / kSplitThreads; ++u) {
         const int f = tid + u * kSplitThreads;
-        const int run = f >> 3, q = f & 7;
-        const int il = run >> 4, ol = run & 15;
-        const int i = ct * 32 + il, o = rt * 16 + ol;
-        if (i < ntx && o < M) Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q] = yst[il * kYCol + ol * kBinBlock + q];
+        const int run = f >> 3, q8 = f & 7;
+        const int il = run / kAng, ol = run % kAng;
+        const int i = ct * 32 + il, o = rt * kAng + ol;
+        if (i < ntx && o < M) Y[((size_t)i * M + o) * kpad + kb * kBinBlock + q8] = buf[il * kCol + ol * kBinBlock + q8];
     }
 }
 
@@ -530,20 +531,21 @@ __global__ __launch_bounds__(kContractThreads, 2) void contract_kernel(const flo
     contract_body<R8>(X, d14, anc, Y, ntx, M, L, ncol, kpad, kb, rt, blockIdx.z, lds);
 }
 
-template <bool F16>
-__global__ __launch_bounds__(kSplitThreads) void contract_split_kernel(
+template <bool F16, int T16>
+__global__ __launch_bounds__(kSplitThreads, 2) void contract_split_kernel(
     const float2* __restrict__ X, const float4* __restrict__ cf, const float2* __restrict__ anc,
     float2* __restrict__ Y, int ntx, int M, int L, int ncol, int kpad, float yscale) {
+    __shared__ __attribute__((aligned(16))) float2 buf[split_lds_float2<T16>()];
     int kb, rt;
-    tile_of(blockIdx.x, (M + 15) / 16, kb, rt);
-    contract_split_body<F16>(X, cf, anc, Y, ntx, M, L, ncol, kpad, yscale, kb, rt, blockIdx.z);
+    tile_of(blockIdx.x, (M + 16 * T16 - 1) / (16 * T16), kb, rt);
+    contract_split_body<F16, T16>(X, cf, anc, Y, ntx, M, L, ncol, kpad, yscale, kb, rt, blockIdx.z, buf);
 }
 
 // Grouped launches over the frames of one FFT-length class: block b runs block b - block0
 // of frame entry blk[b], in the per-frame grid order (bin block fastest, then receive tile,
 // then transmit tile).  PREC: 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo.
 template <int PREC>
-__global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads, PREC == 0 ? 2 : 1) void contract_grouped(
+__global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads, 2) void contract_grouped(
     const ContractEntry* __restrict__ tab, const int32_t* __restrict__ blk, float2* __restrict__ ws) {
     const ContractEntry e = tab[blk[blockIdx.x]];
     int local = (int)blockIdx.x - e.block0;
@@ -563,19 +565,26 @@ __global__ __launch_bounds__(PREC == 0 ? kContractThreads : kSplitThreads, PREC 
             case 3: contract_body<3>(X, d14, anc, Y, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct, lds); break;
             default: contract_body<4>(X, d14, anc, Y, e.ntx, e.M, e.L, e.ncol, e.kpad, kb, rt, ct, lds); break;
         }
-    } else
-        contract_split_body<PREC == 2>(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol, e.kpad,
-                                       e.yscale, kb, rt, ct);
+    } else {
+        __shared__ __attribute__((aligned(16))) float2 buf[split_lds_float2<2>()];
+        if (split_t16(e.M) == 1)
+            contract_split_body<PREC == 2, 1>(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol,
+                                              e.kpad, e.yscale, kb, rt, ct, buf);
+        else
+            contract_split_body<PREC == 2, 2>(ws + e.x_off, pt.cf, pt.anc(e.L), ws + e.y_off, e.ntx, e.M, e.L, e.ncol,
+                                              e.kpad, e.yscale, kb, rt, ct, buf);
+    }
 }
 
 // bins 0 .. n/2 - 1 (the Nyquist bin is summed by the inverse transform)
 // FP32: bin blocks x angle tiles of 8 R8 x column groups of 16; split precision: bin blocks x
-// 16-angle tiles x column groups of 32
-// (x: bin blocks x angle tiles in tile_of order, z: column groups)
+// angle tiles of 16 T16 x column groups of 32 (x: bin blocks x angle tiles in tile_of order,
+// z: column groups)
 dim3 contract_grid(int log2n, int precision, int M, int ntx, int ncol) {
     if (precision == KK_PREC_FP32)
         return dim3(contract_bin_blocks(log2n) * contract_angle_tiles(M), 1, (ntx + kContractCols - 1) / kContractCols);
-    return dim3(contract_bin_blocks(log2n) * ((M + 15) / 16), 1, ncol / 32);
+    const int a = 16 * split_t16(M);
+    return dim3(contract_bin_blocks(log2n) * ((M + a - 1) / a), 1, ncol / 32);
 }
 
 }  // namespace
@@ -609,12 +618,20 @@ hipError_t launch_contract(int log2n, int precision, const float2* X, const Phas
             }
             break;
         case KK_PREC_BF16X3:
-            hipLaunchKernelGGL((contract_split_kernel<false>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
-                               ncol, kpad, 1.0f / xscale);
+            if (split_t16(pt.M) == 1)
+                hipLaunchKernelGGL((contract_split_kernel<false, 1>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M,
+                                   L, ncol, kpad, 1.0f / xscale);
+            else
+                hipLaunchKernelGGL((contract_split_kernel<false, 2>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M,
+                                   L, ncol, kpad, 1.0f / xscale);
             break;
         case KK_PREC_FP16X3:
-            hipLaunchKernelGGL((contract_split_kernel<true>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
-                               ncol, kpad, 1.0f / xscale);
+            if (split_t16(pt.M) == 1)
+                hipLaunchKernelGGL((contract_split_kernel<true, 1>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
+                                   ncol, kpad, 1.0f / xscale);
+            else
+                hipLaunchKernelGGL((contract_split_kernel<true, 2>), grid, block, 0, st, X, pt.cf, anc, Y, ntx, pt.M, L,
+                                   ncol, kpad, 1.0f / xscale);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -264,9 +264,11 @@ int32_t build_plan(const kk_ensemble_frame* frames, int nf, int precision, const
                 c.ncol = w.ncol;
                 c.kpad = w.kpad;
                 c.nkb = (1 << lg) / 2 / kBinBlock;
-                // FP32: angle tiles of 8 R8 and column groups of 16; split: 16 x 32
+                // FP32: angle tiles of 8 R8 and column groups of 16; split: angle tiles of 16 or
+                // 32 (16 T16) and column groups of 32
                 const bool fp32 = precision == KK_PREC_FP32;
-                c.nrt = fp32 ? contract_angle_tiles(in.M) : (in.M + 15) / 16;
+                const int a16 = in.M > 16 ? 32 : 16;
+                c.nrt = fp32 ? contract_angle_tiles(in.M) : (in.M + a16 - 1) / a16;
                 c.block0 = (int32_t)cb.size();
                 c.xscale = a.xscale;
                 c.yscale = 1.0f / a.xscale;
