@@ -302,9 +302,9 @@ def gpu_clocks():
 
 def precision_report(kk, C, torch, np, args):
     """Large workload (192 elements, 75 transmits, 4096 samples, Eq. 6 j = 0, 37, M = 9,
-    384 x 768 pixels): the decomposition in FP32 and in the two split-precision forms, each
-    timed and compared with the FP64 oracle (sampled pixels of the beamformed sets) and with the
-    FP32 run (whole image)."""
+    384 x 768 pixels): the decomposition (phase tables prepared once) in FP32 and in the two
+    split-precision forms, each timed, set against its unfused HBM bound, and compared with the
+    FP64 oracle (sampled pixels of the beamformed sets) and with the FP32 run (whole image)."""
     import oracle as O
     from oracle import frame as OF
     w = C.LARGE
@@ -324,7 +324,9 @@ def precision_report(kk, C, torch, np, args):
         rt = torch.empty((w.N, su.M, w.T), dtype=torch.complex64, device=dev)
         ws = torch.empty(kk.decompose_workspace_bytes(su.geom, w.N, su.M, su.tpad, prec), dtype=torch.uint8,
                          device=dev)
-        ms = timed(lambda: kk.decompose(rf, su.geom, sh, su.M, su.tpad, out=rt, ws=ws, precision=prec),
+        # the phase tables once per geometry, as in the vernier frames
+        kk.decompose_prepare(su.geom, w.N, sh, su.M, su.tpad, ws, precision=prec)
+        ms = timed(lambda: kk.decompose(rf, su.geom, sh, su.M, su.tpad, out=rt, ws=ws, precision=prec, prepared=True),
                    max(5, args.steps // 10), 2, torch)
         img = kk.beamform(rt, su.plan, pd)
         torch.cuda.synchronize()
@@ -333,6 +335,7 @@ def precision_report(kk, C, torch, np, args):
             img32 = got
         out[name] = {
             "decompose_us": round(ms * 1e3, 2),
+            "frac_unfused_hbm": round(_decompose_bytes(w.N, w.L, w.T, su.M, su.tpad) / HBM_BYTES_PER_S / (ms * 1e-3), 4),
             "rel_l2_rf_theta_vs_fp64": float(np.linalg.norm(rt.cpu().numpy() - R64) / np.linalg.norm(R64)),
             "rel_l2_image_vs_fp64": float(np.linalg.norm(got[:, xi, zi] - ref) / np.linalg.norm(ref)),
             "rel_l2_image_vs_fp32": float(np.linalg.norm(got - img32) / np.linalg.norm(img32)),

@@ -39,7 +39,9 @@ def _tol(K, prec):
 @pytest.mark.parametrize("prec_name", ["PREC_BF16X3", "PREC_FP16X3"])
 @pytest.mark.parametrize("N,L,T,M,tpad,seed", [
     (3, 5, 200, 4, 256, 1),
-    (5, 7, 333, 17, 512, 2),       # two receive-angle tiles
+    (5, 7, 333, 17, 512, 2),       # two 16-angle MFMA tiles in one workgroup
+    (4, 9, 700, 32, 1024, 7),      # 32 angles in one workgroup
+    (3, 5, 400, 45, 512, 8),       # two 32-angle workgroups, the second past the tables
     (33, 6, 1000, 3, 1024, 3),     # two transmit tiles
     (1, 3, 5000, 2, 8192, 6),      # longest records: the FP16 prescale's extreme
 ])
