@@ -110,10 +110,13 @@ __device__ __forceinline__ void load_meta(SlotMeta& m, const int32_t* __restrict
 }
 
 // Issues the global loads of pair q (window entries and delays); j = q - (first pair of the
-// metadata run) selects the pair's metadata lane.
+// metadata run) selects the pair's metadata lane.  A window inside its record is read through a
+// buffer view of the record at the window start (a wave-uniform offset, no vector address
+// arithmetic); a window over a record edge reads zeros outside the record, sample by sample.
+// The delays come through the plan's view at wave-uniform offsets (in range by the plan).
 template <int CAP, bool DAS>
 __device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const SlotMeta& m, int j,
-                                          const float2* __restrict__ rec, const int32_t* __restrict__ plan,
+                                          const float2* __restrict__ rec, __amdgpu_buffer_rsrc_t pview,
                                           const PlanView& pv, int q, int lane) {
     const unsigned ulane = (unsigned)lane;
     const int lo = __builtin_amdgcn_readlane(m.lo, j);
@@ -121,9 +124,12 @@ __device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const 
     const float2* rp = rec + (size_t)ri * pv.T;
     if (lo >= 0 && lo + CAP <= pv.T - 1) {
         // the whole window and its right neighbours lie inside the record
-        const float2* src = rp + lo;
+        const __amdgpu_buffer_rsrc_t rv = buffer_view(rp, (uint32_t)pv.T * sizeof(float2));
 #pragma unroll
-        for (int r = 0; r < CAP / 64; ++r) wn.v[r] = *reinterpret_cast<const F4a8*>(src + r * 64 + ulane);
+        for (int r = 0; r < CAP / 64; ++r) {
+            const float4 v = buffer_load4(rv, (ulane + r * 64) * sizeof(float2), (uint32_t)lo * sizeof(float2));
+            wn.v[r] = F4a8{v.x, v.y, v.z, v.w};
+        }
     } else {
 #pragma unroll
         for (int r = 0; r < CAP / 64; ++r) {
@@ -134,8 +140,8 @@ __device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const 
         }
     }
     const int row = delay_row<DAS>(q, pv.N);
-    d.a = (uint32_t)(plan + pv.off_a + pv.xt * 64 + (unsigned)(row * pv.xpad))[ulane];
-    d.b = (uint32_t)(plan + pv.off_b + pv.zt * kRows + (unsigned)(row * pv.zpad))[ulane & 15];
+    d.a = buffer_load1(pview, ulane * 4, (uint32_t)(pv.off_a + pv.xt * 64 + row * pv.xpad) * 4);
+    d.b = buffer_load1(pview, (ulane & 15) * 4, (uint32_t)(pv.off_b + pv.zt * kRows + row * pv.zpad) * 4);
     d.lo = lo;
 }
 
@@ -287,6 +293,8 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
     for (int k = 0; k < kRows; ++k) acc[k] = make_float2(0.f, 0.f);
 
     float4* slot = reinterpret_cast<float4*>(lds) + wave * CAP;
+    // the plan's words through a buffer view (every offset taken through it is in range)
+    const __amdgpu_buffer_rsrc_t pview = buffer_view(plan, 0x7FFFFFFCu);
     if (w_begin < w_end) {
         Window<CAP> wn;
         PairDelays cur, nxt_d;
@@ -295,7 +303,7 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
         int c_elem = -1;
         int m_base = w_begin;
         load_meta(meta, plan, pv, m_base, w_end, lane);
-        load_pair<CAP, DAS>(wn, cur, meta, 0, rec, plan, pv, w_begin, lane);
+        load_pair<CAP, DAS>(wn, cur, meta, 0, rec, pview, pv, w_begin, lane);
         fold_delays<CAP>(cur, wave);
         store_window<CAP>(wn, slot, lane);
         // the first pair's delays are complete before the loop, so the loop's only loads in
@@ -308,7 +316,7 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
                     m_base = q + 1;
                     load_meta(meta, plan, pv, m_base, w_end, lane);
                 }
-                load_pair<CAP, DAS>(wn, nxt_d, meta, q + 1 - m_base, rec, plan, pv, q + 1, lane);
+                load_pair<CAP, DAS>(wn, nxt_d, meta, q + 1 - m_base, rec, pview, pv, q + 1, lane);
             }
             if constexpr (DAS) {
                 const int l = q / pv.N;

@@ -67,19 +67,6 @@ __device__ __forceinline__ float2 cmul2(float2 a, float2 b) {
     return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
-// Raw buffer view of nbytes at p (gfx9 descriptor: 32-bit data format, no swizzle): loads take
-// a per-lane and a wave-uniform byte offset with no vector address arithmetic, and loads past
-// nbytes return zero.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void* p, uint32_t nbytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
-}
-__device__ __forceinline__ float2 buffer_load2(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane_off, (int)off, 0));
-}
-__device__ __forceinline__ float4 buffer_load4(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
-    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)lane_off, (int)off, 0));
-}
-
 // Anchors of elements [c0, c0 + cn) of one bin block and receive tile (split kernel): global ->
 // registers -> LDS rows [l - c0][16] (indexes past the chunk re-read its last piece).
 __device__ __forceinline__ void stage_anchors(float2* buf, const float2* __restrict__ anc, int c0, int cn, int tid) {

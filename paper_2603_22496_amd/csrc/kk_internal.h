@@ -16,6 +16,23 @@ namespace kk {
 // (Re, Im) and the lo pair, each as one 32-bit word with Re in the low half.
 constexpr int kBinBlock = 8;
 
+// Raw buffer view of nbytes at p (gfx9 descriptor: 32-bit data format, no swizzle): loads take
+// a per-lane and a wave-uniform byte offset with no vector address arithmetic; a load whose
+// per-lane offset lies at or past nbytes returns zero (the wave-uniform offset is not part of
+// that check, so callers keep it in range themselves).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void* p, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nbytes, 0x00020000);
+}
+__device__ __forceinline__ uint32_t buffer_load1(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)lane_off, (int)off, 0);
+}
+__device__ __forceinline__ float2 buffer_load2(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)lane_off, (int)off, 0));
+}
+__device__ __forceinline__ float4 buffer_load4(__amdgpu_buffer_rsrc_t r, uint32_t lane_off, uint32_t off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)lane_off, (int)off, 0));
+}
+
 // x = hi + lo with hi = round16(x), lo = round16(x - hi), round16 = BF16 or FP16 rounding to
 // nearest even: the bits of (hi of a, hi of b) and (lo of a, lo of b), a in the low halves.
 typedef float kk_float2v __attribute__((ext_vector_type(2)));
