@@ -324,8 +324,8 @@ __device__ __forceinline__ void contract_body(const float2* __restrict__ X, cons
 // (FP16) of the terms.  The forward transform stores the spectrum already split (its 8 bytes
 // per bin: the hi pair and the lo pair), so the B operands are loaded words; FP16 spectra are
 // scaled by 2^e before the split so that |X| < 2^15 (|X| <= 2 T 32768 for int16 records), and
-// Y by 2^-e here (both exact).  Workgroup: one bin block, 16 receive angles, 32 transmits;
-// wave w takes bin pair w % 4 over half w / 4 of the elements, the halves summed at the end.
+// Y by 2^-e here (both exact).  Workgroup: one bin block, 16 T16 receive angles (one or two
+// MFMA row tiles per wave), 32 transmits; wave w takes bin pair w over all elements.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
