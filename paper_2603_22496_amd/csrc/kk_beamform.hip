@@ -140,8 +140,11 @@ __device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const 
         }
     }
     const int row = delay_row<DAS>(q, pv.N);
-    d.a = buffer_load1(pview, ulane * 4, (uint32_t)(pv.off_a + pv.xt * 64 + row * pv.xpad) * 4);
-    d.b = buffer_load1(pview, (ulane & 15) * 4, (uint32_t)(pv.off_b + pv.zt * kRows + row * pv.zpad) * 4);
+    // (the offsets are uniform; readfirstlane lets the loads take them as scalars)
+    const uint32_t oa = (uint32_t)__builtin_amdgcn_readfirstlane((pv.off_a + pv.xt * 64 + row * pv.xpad) * 4);
+    const uint32_t ob = (uint32_t)__builtin_amdgcn_readfirstlane((pv.off_b + pv.zt * kRows + row * pv.zpad) * 4);
+    d.a = buffer_load1(pview, ulane * 4, oa);
+    d.b = buffer_load1(pview, (ulane & 15) * 4, ob);
     d.lo = lo;
 }
 
