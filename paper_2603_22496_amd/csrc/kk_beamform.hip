@@ -82,9 +82,9 @@ struct Window {
 
 // Delays of one pair for one wave.
 struct PairDelays {
-    uint32_t a;   // lateral delay at pixel `lane`
-    uint32_t b;   // axial delay of row (lane & 15); window start and slot folded in once loaded
-    int32_t lo;   // window start (uniform)
+    uint32_t a;     // lateral delay at pixel `lane`
+    uint32_t b;     // axial delay of row (lane & 15); window start and slot folded in once loaded
+    uint32_t fold;  // (slot start - window start) << 16 (uniform)
 };
 
 struct PlanView {
@@ -117,7 +117,7 @@ __device__ __forceinline__ void load_meta(SlotMeta& m, const int32_t* __restrict
 template <int CAP, bool DAS>
 __device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const SlotMeta& m, int j,
                                           const float2* __restrict__ rec, __amdgpu_buffer_rsrc_t pview,
-                                          const PlanView& pv, int q, int lane) {
+                                          const PlanView& pv, int q, int slot0, int lane) {
     const unsigned ulane = (unsigned)lane;
     const int lo = __builtin_amdgcn_readlane(m.lo, j);
     const int ri = __builtin_amdgcn_readlane(m.rec, j);
@@ -145,15 +145,12 @@ __device__ __forceinline__ void load_pair(Window<CAP>& wn, PairDelays& d, const 
     const uint32_t ob = (uint32_t)__builtin_amdgcn_readfirstlane((pv.off_b + pv.zt * kRows + row * pv.zpad) * 4);
     d.a = buffer_load1(pview, ulane * 4, oa);
     d.b = buffer_load1(pview, (ulane & 15) * 4, ob);
-    d.lo = lo;
+    d.fold = (uint32_t)(slot0 - lo) << 16;
 }
 
 // Folds the window start and the wave's slot into the axial delays once their loads have
 // landed (called after the gather of the previous pair, so the loads stay in flight during it).
-template <int CAP>
-__device__ __forceinline__ void fold_delays(PairDelays& d, int wave) {
-    d.b += (uint32_t)(wave * CAP - d.lo) << 16;
-}
+__device__ __forceinline__ void fold_delays(PairDelays& d) { d.b += d.fold; }
 
 template <int CAP>
 __device__ __forceinline__ void store_window(const Window<CAP>& wn, float4* slot, int lane) {
@@ -306,8 +303,8 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
         int c_elem = -1;
         int m_base = w_begin;
         load_meta(meta, plan, pv, m_base, w_end, lane);
-        load_pair<CAP, DAS>(wn, cur, meta, 0, rec, pview, pv, w_begin, lane);
-        fold_delays<CAP>(cur, wave);
+        load_pair<CAP, DAS>(wn, cur, meta, 0, rec, pview, pv, w_begin, wave * CAP, lane);
+        fold_delays(cur);
         store_window<CAP>(wn, slot, lane);
         // the first pair's delays are complete before the loop, so the loop's only loads in
         // flight during a gather are the next pair's
@@ -319,7 +316,7 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
                     m_base = q + 1;
                     load_meta(meta, plan, pv, m_base, w_end, lane);
                 }
-                load_pair<CAP, DAS>(wn, nxt_d, meta, q + 1 - m_base, rec, pview, pv, q + 1, lane);
+                load_pair<CAP, DAS>(wn, nxt_d, meta, q + 1 - m_base, rec, pview, pv, q + 1, wave * CAP, lane);
             }
             if constexpr (DAS) {
                 const int l = q / pv.N;
@@ -334,7 +331,7 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
             }
             gather_pair<DAS, (!DAS && CAP <= 320) ? 3 : 2>(acc, cur, c, reinterpret_cast<const unsigned char*>(lds));
             if (more) {
-                fold_delays<CAP>(nxt_d, wave);
+                fold_delays(nxt_d);
                 // the gather's reads of the slot precede these stores in the wave's LDS order
                 __builtin_amdgcn_sched_barrier(0);
                 store_window<CAP>(wn, slot, lane);
