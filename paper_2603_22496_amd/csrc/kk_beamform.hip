@@ -309,14 +309,16 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
         // the first pair's delays are complete before the loop, so the loop's only loads in
         // flight during a gather are the next pair's
         asm volatile("" ::"v"(cur.a), "v"(cur.b));
-        for (int q = w_begin; q < w_end; ++q) {
+        // pair q gathers with the delays in `use` while pair q + 1's loads land in `next`; the
+        // loop runs two pairs per pass with the two delay sets swapping roles (no copies)
+        auto step = [&](int q, const PairDelays& use, PairDelays& next) {
             const bool more = q + 1 < w_end;
             if (more) {
                 if (q + 1 - m_base == kMetaLanes) {
                     m_base = q + 1;
                     load_meta(meta, plan, pv, m_base, w_end, lane);
                 }
-                load_pair<CAP, DAS>(wn, nxt_d, meta, q + 1 - m_base, rec, pview, pv, q + 1, wave * CAP, lane);
+                load_pair<CAP, DAS>(wn, next, meta, q + 1 - m_base, rec, pview, pv, q + 1, wave * CAP, lane);
             }
             if constexpr (DAS) {
                 const int l = q / pv.N;
@@ -329,14 +331,17 @@ __device__ __forceinline__ void gather_body(const float2* __restrict__ rec, cons
                     for (int k = 0; k < kRows; ++k) c[k] = (uint32_t)crow[(unsigned)(k * pv.xpad) + (unsigned)lane];
                 }
             }
-            gather_pair<DAS, (!DAS && CAP <= 320) ? 3 : 2>(acc, cur, c, reinterpret_cast<const unsigned char*>(lds));
+            gather_pair<DAS, (!DAS && CAP <= 320) ? 3 : 2>(acc, use, c, reinterpret_cast<const unsigned char*>(lds));
             if (more) {
-                fold_delays(nxt_d);
+                fold_delays(next);
                 // the gather's reads of the slot precede these stores in the wave's LDS order
                 __builtin_amdgcn_sched_barrier(0);
                 store_window<CAP>(wn, slot, lane);
-                cur = nxt_d;
             }
+        };
+        for (int q = w_begin; q < w_end; q += 2) {
+            step(q, cur, nxt_d);
+            if (q + 1 < w_end) step(q + 1, nxt_d, cur);
         }
     }
     // sum the waves' partial tiles in wave order
